@@ -1,0 +1,163 @@
+/*
+ * gjp.h -- C ABI of the MI355X (gfx950) generalized Joseph projector.
+ *
+ * The projector follows Sec. III of Graetz, "High performance volume ray
+ * casting: a branchless generalized Joseph projector" (arXiv 1609.00958):
+ * each ray is stepped one voxel plane at a time along its driving axis
+ * (Eqs. 1-6), the two transverse axes are interpolated from the four in-plane
+ * neighbours (Eqs. 7-12, weight functions Eqs. 13-14) and the sum is scaled by
+ * the step length (Algorithm 1).
+ *
+ * Conventions (all functions):
+ *   - Volumes are C-order arrays vol[n0][n1][n2] (n2 fastest). Grid
+ *     coordinate k is the centre of voxel k; world -> grid for a point w is
+ *         g_k = (w_k - vol_center_k) / voxel_size_k + (n_k - 1) * 0.5
+ *     and for a direction g_k = w_k / voxel_size_k (double precision, no
+ *     fused multiply-add).
+ *   - A view is 12 doubles in world units. Cone beam: src[3], det00[3],
+ *     du[3], dv[3]; parallel beam: dir[3], det00[3], du[3], dv[3]. The centre
+ *     of pixel (iu, iv) is det00 + iu*du + iv*dv (evaluated left to right).
+ *     For a parallel beam the pixel itself is the ray's reference point.
+ *   - Sinograms are C-order float arrays sino[n_views][n_u][n_v] (v fastest).
+ *   - A sample (ray, plane i) exists when -1 < p_k < n_k on both transverse
+ *     axes and 0 <= i < n_m (the volume is read as zero outside the grid);
+ *     the driving axis is argmax |r_k| with ties to the lowest axis index. The
+ *     ray setup and the sample range are evaluated in double precision;
+ *     sample positions, weights and accumulation in single precision.
+ *   - Device pointers must point to memory of the current HIP device; the
+ *     library never frees caller memory. `stream` is a hipStream_t (NULL for
+ *     the default stream); every projection call is asynchronous on it.
+ *   - Every function returns a gjp_status. Arguments are validated before any
+ *     GPU work is queued; on failure nothing is launched and
+ *     gjp_last_error() describes the problem. No C++ exception crosses the ABI.
+ */
+#ifndef GJP_H
+#define GJP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GJP_OK = 0,
+  GJP_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad enum) */
+  GJP_ENOMEM = -2,       /* host or device allocation failed */
+  GJP_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+  GJP_EUNSUPPORTED = -4  /* valid request that this build does not implement */
+} gjp_status;
+
+typedef enum { GJP_F32 = 0, GJP_BF16 = 1, GJP_F16 = 2 } gjp_dtype;
+typedef enum { GJP_CONE = 0, GJP_PARALLEL = 1 } gjp_beam;
+/* Eq. 13 (linear, classic multilinear interpolation) and Eq. 14 (cubic
+   smoothstep spline, differentiable at grid points). */
+typedef enum { GJP_W_LINEAR = 0, GJP_W_SPLINE = 1 } gjp_weight;
+
+typedef struct {
+  int32_t vol_shape[3];   /* n0, n1, n2 (n2 fastest); each >= 1 */
+  double voxel_size[3];   /* world units per grid step; each > 0 */
+  double vol_center[3];   /* world position of the grid centre */
+  int32_t n_views, n_u, n_v;
+  int32_t beam;           /* gjp_beam */
+  const double *views;    /* host, n_views x 12 doubles (world units); copied */
+  int32_t weight;         /* gjp_weight */
+  uint32_t flags;         /* reserved, must be 0 */
+} gjp_geometry_desc;
+
+typedef struct gjp_geometry gjp_geometry; /* opaque, immutable after creation */
+
+/* Create a projection geometry (Sec. III-A: source and detector pixel
+   positions in grid units). Host-only: validates `desc`, copies the view
+   vectors and converts them to grid units; device copies are made on first
+   use on each device. *out receives the handle (caller destroys it).
+   Errors: GJP_EINVAL for a null pointer, a non-positive size, a
+   non-positive voxel size, an unknown beam/weight, non-zero flags, a
+   non-finite view vector, or more than 32767 voxels along an axis;
+   GJP_ENOMEM if the copy cannot be allocated. */
+gjp_status gjp_create_geometry(const gjp_geometry_desc *desc, gjp_geometry **out);
+
+/* Destroy a geometry and its device copies. NULL is accepted. The caller
+   must make sure no queued projection still uses it. */
+gjp_status gjp_destroy_geometry(gjp_geometry *g);
+
+/* Forward projection y = A x (Algorithm 1, one ray per detector pixel).
+   d_vol: device, n0*n1*n2 elements of `vol_dtype` (gjp_dtype), C order,
+   aligned to its element size. d_sino: device, n_views*n_u*n_v floats,
+   overwritten. BF16/FP16 volumes are widened to FP32 in registers; the
+   accumulation is FP32 in every case. A zero-padded copy of the volume is
+   taken from the stream-ordered pool for the duration of the call.
+   Errors: GJP_EINVAL (null pointer, unknown dtype), GJP_ENOMEM, GJP_EHIP. */
+gjp_status gjp_forward_project(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
+                               float *d_sino, void *stream);
+
+/* Adjoint (exact transpose) x = A^T y of gjp_forward_project for the same
+   geometry: every sample's single-precision weights are recomputed exactly as
+   the forward computes them, and each voxel gathers its contributions from
+   the candidate rays of every view (voxel-driven, no atomic accumulation;
+   the result is bitwise reproducible). d_sino: device, n_views*n_u*n_v
+   floats. d_vol: device, n0*n1*n2 floats, overwritten. Per-ray tables for a
+   chunk of views are taken from the stream-ordered pool during the call.
+   Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
+gjp_status gjp_back_project(const gjp_geometry *g, const float *d_sino, float *d_vol,
+                            void *stream);
+
+/* Batched forward projection of n independent instances (geometry, volume,
+   dtype, sinogram) in one persistent launch: work items (instance, view, ray
+   tile) are ordered longest-first and pulled from a device queue; the launch
+   sequence is captured in a HIP graph on first use for a given list of
+   geometries and replayed afterwards. Each sinogram is bitwise equal to the
+   one gjp_forward_project produces for the same instance and tile shape.
+   Arrays g, d_vols, dtypes, d_sinos are host arrays of length n >= 1.
+   Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
+gjp_status gjp_forward_project_batched(int32_t n, const gjp_geometry *const *g,
+                                       const void *const *d_vols, const int32_t *dtypes,
+                                       float *const *d_sinos, void *stream);
+
+/* Circular cone-beam trajectory about axis 2 (the paper's benchmark setup,
+   Sec. IV-C): view k at angle 2*pi*k/n_views counter-clockwise, source at
+   (sod cos, sod sin, 0), flat detector centred on the central ray at
+   distance sdd from the source, du = pitch_u (-sin, cos, 0), dv = (0, 0,
+   pitch_v). World units, volume centred at the origin. out_views: host,
+   n_views x 12 doubles. Errors: GJP_EINVAL. */
+gjp_status gjp_views_circular_cone(int32_t n_views, double sod, double sdd, double pitch_u,
+                                   double pitch_v, int32_t n_u, int32_t n_v, double *out_views);
+
+/* Circular parallel-beam trajectory: dir = (-cos, -sin, 0), detector plane
+   through the rotation axis, du and dv as above. Errors: GJP_EINVAL. */
+gjp_status gjp_views_parallel(int32_t n_views, double pitch_u, double pitch_v, int32_t n_u,
+                              int32_t n_v, double *out_views);
+
+/* Exact number of samples (ray, plane) of the whole sinogram, from the same
+   double-precision ray setup the kernels run (host, multithreaded). This is
+   the ray-sample count of the throughput metric. Errors: GJP_EINVAL. */
+gjp_status gjp_count_samples(const gjp_geometry *g, uint64_t *out);
+
+/* Select the ray-tile shape of gjp_forward_project for this geometry and
+   dtype by timing each candidate on `stream` with the caller's buffers
+   (d_sino is overwritten). The choice is kept in a process-wide cache keyed
+   by the geometry's shape signature and dtype and used by later forward and
+   batched calls. *tile_v_out receives the chosen number of detector pixels
+   along v per wavefront row (64, 32 or 16). Synchronises `stream`.
+   Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
+gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
+                                float *d_sino, void *stream, int32_t *tile_v_out);
+
+/* Per-kernel GPU timing for benchmarks. While enabled, each launch of the
+   library's main kernels is bracketed by HIP events on its stream.
+   gjp_timing_read waits for those events and returns the total time in
+   milliseconds and the number of launches recorded for `kernel` ("forward",
+   "pad", "adjoint_table", "adjoint_gather", "batched"). */
+gjp_status gjp_timing_enable(int32_t on);
+gjp_status gjp_timing_reset(void);
+gjp_status gjp_timing_read(const char *kernel, double *total_ms, int64_t *launches);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *gjp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GJP_H */

@@ -19,6 +19,9 @@ def build(force: bool = True) -> str:
     cmd = [
         "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+        # keep sin and cos as separate libm calls (no merge into sincos, which can
+        # round differently in the last bit)
+        "-fno-builtin-sin", "-fno-builtin-cos", "-fno-builtin-sincos",
         SRC, "-o", tmp, "-lm",
     ]
     subprocess.check_call(cmd)

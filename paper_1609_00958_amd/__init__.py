@@ -1,0 +1,20 @@
+"""MI355X (gfx950) generalized Joseph projector (arXiv 1609.00958).
+
+Forward X-ray projection of a voxel grid with driving-axis aligned sampling
+and four-neighbour interpolation (Sec. III, Algorithm 1), its exact adjoint,
+BF16/FP16 volume storage and a batched persistent launch, all in hand-written
+HIP kernels behind the C ABI declared in include/gjp.h.
+"""
+from ._lib import (BF16, CONE, F16, F32, PARALLEL, W_LINEAR, W_SPLINE, GJPError,  # noqa: F401
+                   lib)
+from .projector import (Geometry, autotune, back, forward, forward_batched,  # noqa: F401
+                        project, timing_enable, timing_read, timing_reset, views_circular_cone,
+                        views_parallel)
+
+lib()  # load the HIP library now: there is no fallback path
+
+__all__ = [
+    "Geometry", "forward", "back", "forward_batched", "project", "autotune",
+    "views_circular_cone", "views_parallel", "timing_enable", "timing_read", "timing_reset",
+    "GJPError",
+]

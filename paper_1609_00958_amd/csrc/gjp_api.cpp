@@ -1,0 +1,855 @@
+// gjp_api.cpp -- C ABI of the generalized Joseph projector (see include/gjp.h).
+//
+// Host responsibilities: argument validation, world -> grid conversion of the
+// view vectors (double precision, no contraction), per-view detector
+// projection rows for the adjoint's candidate search, stream-ordered scratch
+// (zero-padded volume copies, adjoint ray tables), the forward tile
+// autotuner, kernel timing for benchmarks, and the batched plan (work list,
+// device queue, HIP graph).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/gjp.h"
+#include "gjp_internal.h"
+
+using gjp::BatchInst;
+using gjp::FwdArgs;
+using gjp::FwdTile;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+int gjp::set_error(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+static gjp_status fail(gjp_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+static gjp_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? GJP_ENOMEM : GJP_EHIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GJP_HIP(call, what)                    \
+  do {                                         \
+    hipError_t _e = (call);                    \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+extern "C" const char* gjp_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------
+namespace {
+struct TimingState {
+  std::mutex mu;
+  bool on = false;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::map<std::string, std::pair<double, int64_t>> total;
+};
+TimingState& timing() {
+  static TimingState* t = new TimingState();
+  return *t;
+}
+}  // namespace
+
+gjp::TimedLaunch gjp::timing_begin(const char* name, hipStream_t s) {
+  (void)name;
+  TimedLaunch t;
+  TimingState& T = timing();
+  {
+    std::lock_guard<std::mutex> lk(T.mu);
+    if (!T.on) return t;
+  }
+  if (hipEventCreate(&t.start) != hipSuccess) return t;
+  if (hipEventCreate(&t.stop) != hipSuccess) {
+    (void)hipEventDestroy(t.start);
+    t.start = nullptr;
+    return t;
+  }
+  if (hipEventRecord(t.start, s) != hipSuccess) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+    t.start = t.stop = nullptr;
+    return t;
+  }
+  t.on = true;
+  return t;
+}
+
+void gjp::timing_end(const char* name, TimedLaunch& t, hipStream_t s) {
+  if (!t.on) return;
+  (void)hipEventRecord(t.stop, s);
+  TimingState& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.pending[name].push_back({t.start, t.stop});
+}
+
+extern "C" gjp_status gjp_timing_enable(int32_t on) {
+  TimingState& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.on = (on != 0);
+  return GJP_OK;
+}
+
+extern "C" gjp_status gjp_timing_reset(void) {
+  TimingState& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  for (auto& kv : T.pending)
+    for (auto& ev : kv.second) {
+      (void)hipEventSynchronize(ev.second);
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+  T.pending.clear();
+  T.total.clear();
+  return GJP_OK;
+}
+
+extern "C" gjp_status gjp_timing_read(const char* kernel, double* total_ms, int64_t* launches) {
+  if (!kernel || !total_ms || !launches) return fail(GJP_EINVAL, "gjp_timing_read: null pointer");
+  TimingState& T = timing();
+  std::lock_guard<std::mutex> lk(T.mu);
+  auto it = T.pending.find(kernel);
+  if (it != T.pending.end()) {
+    for (auto& ev : it->second) {
+      GJP_HIP(hipEventSynchronize(ev.second), "timing event");
+      float ms = 0.0f;
+      GJP_HIP(hipEventElapsedTime(&ms, ev.first, ev.second), "timing elapsed");
+      auto& tot = T.total[kernel];
+      tot.first += ms;
+      tot.second += 1;
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    it->second.clear();
+  }
+  auto jt = T.total.find(kernel);
+  *total_ms = (jt == T.total.end()) ? 0.0 : jt->second.first;
+  *launches = (jt == T.total.end()) ? 0 : jt->second.second;
+  return GJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// trajectories
+// ---------------------------------------------------------------------------
+static const double kPi = 3.14159265358979323846;
+
+extern "C" gjp_status gjp_views_circular_cone(int32_t n_views, double sod, double sdd,
+                                              double pitch_u, double pitch_v, int32_t n_u,
+                                              int32_t n_v, double* out) {
+  if (n_views <= 0 || n_u <= 0 || n_v <= 0 || !out)
+    return fail(GJP_EINVAL, "gjp_views_circular_cone: non-positive size or null output");
+  if (!isfinite(sod) || !isfinite(sdd) || !isfinite(pitch_u) || !isfinite(pitch_v))
+    return fail(GJP_EINVAL, "gjp_views_circular_cone: non-finite parameter");
+  for (int k = 0; k < n_views; ++k) {
+    const double th = 2.0 * kPi * (double)k / (double)n_views;
+    const double c = cos(th), s = sin(th);
+    double* o = out + 12 * (size_t)k;
+    const double src[3] = {sod * c, sod * s, 0.0};
+    const double dc[3] = {(sod - sdd) * c, (sod - sdd) * s, 0.0};
+    const double du[3] = {-pitch_u * s, pitch_u * c, 0.0};
+    const double dv[3] = {0.0, 0.0, pitch_v};
+    const double hu = 0.5 * (double)(n_u - 1), hv = 0.5 * (double)(n_v - 1);
+    for (int j = 0; j < 3; ++j) {
+      o[0 + j] = src[j];
+      o[3 + j] = dc[j] - hu * du[j] - hv * dv[j];
+      o[6 + j] = du[j];
+      o[9 + j] = dv[j];
+    }
+  }
+  return GJP_OK;
+}
+
+extern "C" gjp_status gjp_views_parallel(int32_t n_views, double pitch_u, double pitch_v,
+                                         int32_t n_u, int32_t n_v, double* out) {
+  if (n_views <= 0 || n_u <= 0 || n_v <= 0 || !out)
+    return fail(GJP_EINVAL, "gjp_views_parallel: non-positive size or null output");
+  if (!isfinite(pitch_u) || !isfinite(pitch_v))
+    return fail(GJP_EINVAL, "gjp_views_parallel: non-finite parameter");
+  for (int k = 0; k < n_views; ++k) {
+    const double th = 2.0 * kPi * (double)k / (double)n_views;
+    const double c = cos(th), s = sin(th);
+    double* o = out + 12 * (size_t)k;
+    const double dir[3] = {-c, -s, 0.0};
+    const double du[3] = {-pitch_u * s, pitch_u * c, 0.0};
+    const double dv[3] = {0.0, 0.0, pitch_v};
+    const double hu = 0.5 * (double)(n_u - 1), hv = 0.5 * (double)(n_v - 1);
+    for (int j = 0; j < 3; ++j) {
+      o[0 + j] = dir[j];
+      o[3 + j] = 0.0 - hu * du[j] - hv * dv[j];
+      o[6 + j] = du[j];
+      o[9 + j] = dv[j];
+    }
+  }
+  return GJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+static std::atomic<uint64_t> g_next_id{1};
+
+static void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Rows (u, v, w) mapping a grid point q to homogeneous detector coordinates
+// (continuous pixel indices): u = (A_u.q + b_u) / (A_w.q + b_w), w > 0 in
+// front of the source. Used only to bound the adjoint's candidate rays.
+static void detector_projection(const double* v, int beam, float* P) {
+  const double* o = v + 3;
+  const double* du = v + 6;
+  const double* dv = v + 9;
+  double n[3], t1[3], t2[3], eu[3], ev[3];
+  cross3(du, dv, n);
+  cross3(dv, n, t1);
+  cross3(n, du, t2);
+  const double su = dot3(du, t1), sv = dot3(dv, t2);
+  for (int k = 0; k < 3; ++k) {
+    eu[k] = (su != 0.0) ? t1[k] / su : 0.0;
+    ev[k] = (sv != 0.0) ? t2[k] / sv : 0.0;
+  }
+  double R[12];
+  if (beam == gjp::BEAM_CONE) {
+    const double* s = v;
+    double som[3] = {s[0] - o[0], s[1] - o[1], s[2] - o[2]};
+    const double K = -dot3(n, som);  // n.(o - s)
+    const double ns = dot3(n, s);
+    const double eus = dot3(eu, som), evs = dot3(ev, som);
+    for (int k = 0; k < 3; ++k) {
+      R[k] = eus * n[k] + K * eu[k];
+      R[4 + k] = evs * n[k] + K * ev[k];
+      R[8 + k] = n[k];
+    }
+    R[3] = -eus * ns - K * dot3(eu, s);
+    R[7] = -evs * ns - K * dot3(ev, s);
+    R[11] = -ns;
+    if (K < 0.0)
+      for (int k = 0; k < 12; ++k) R[k] = -R[k];
+  } else {
+    const double* r = v;
+    const double nr = dot3(n, r);
+    const double au = (nr != 0.0) ? dot3(eu, r) / nr : 0.0;
+    const double av = (nr != 0.0) ? dot3(ev, r) / nr : 0.0;
+    const double no = dot3(n, o);
+    for (int k = 0; k < 3; ++k) {
+      R[k] = eu[k] - au * n[k];
+      R[4 + k] = ev[k] - av * n[k];
+      R[8 + k] = 0.0;
+    }
+    R[3] = -dot3(eu, o) + au * no;
+    R[7] = -dot3(ev, o) + av * no;
+    R[11] = 1.0;
+  }
+  for (int k = 0; k < 12; ++k) P[k] = (float)R[k];
+}
+
+extern "C" gjp_status gjp_create_geometry(const gjp_geometry_desc* d, gjp_geometry** out) {
+  if (!d || !out) return fail(GJP_EINVAL, "gjp_create_geometry: null pointer");
+  *out = nullptr;
+  for (int k = 0; k < 3; ++k) {
+    if (d->vol_shape[k] <= 0 || d->vol_shape[k] > 32767)
+      return fail(GJP_EINVAL, "gjp_create_geometry: vol_shape must be in [1, 32767]");
+    if (!(d->voxel_size[k] > 0.0) || !isfinite(d->voxel_size[k]))
+      return fail(GJP_EINVAL, "gjp_create_geometry: voxel_size must be positive and finite");
+    if (!isfinite(d->vol_center[k]))
+      return fail(GJP_EINVAL, "gjp_create_geometry: vol_center must be finite");
+  }
+  if (d->n_views <= 0 || d->n_u <= 0 || d->n_v <= 0)
+    return fail(GJP_EINVAL, "gjp_create_geometry: n_views, n_u and n_v must be positive");
+  if (d->beam != GJP_CONE && d->beam != GJP_PARALLEL)
+    return fail(GJP_EINVAL, "gjp_create_geometry: unknown beam");
+  if (d->weight != GJP_W_LINEAR && d->weight != GJP_W_SPLINE)
+    return fail(GJP_EINVAL, "gjp_create_geometry: unknown weight function");
+  if (d->flags != 0) return fail(GJP_EINVAL, "gjp_create_geometry: flags must be 0");
+  if (!d->views) return fail(GJP_EINVAL, "gjp_create_geometry: views is null");
+  const size_t nv = (size_t)d->n_views;
+  if ((unsigned long long)d->n_views * d->n_u * d->n_v > (1ull << 46))
+    return fail(GJP_EINVAL, "gjp_create_geometry: sinogram too large");
+  for (size_t i = 0; i < 12 * nv; ++i)
+    if (!isfinite(d->views[i])) return fail(GJP_EINVAL, "gjp_create_geometry: non-finite view");
+  if (d->n_views >= (1 << 20))
+    return fail(GJP_EINVAL, "gjp_create_geometry: at most 2^20 - 1 views");
+
+  std::unique_ptr<gjp_geometry> g;
+  try {
+    g.reset(new gjp_geometry());
+    g->views_world.assign(d->views, d->views + 12 * nv);
+    g->views_grid.resize(12 * nv);
+    g->proj.resize(12 * nv);
+  } catch (...) {
+    return fail(GJP_ENOMEM, "gjp_create_geometry: host allocation failed");
+  }
+  g->id = g_next_id.fetch_add(1);
+  for (int k = 0; k < 3; ++k) {
+    g->n[k] = d->vol_shape[k];
+    g->vs[k] = d->voxel_size[k];
+    g->ctr[k] = d->vol_center[k];
+    g->gg.n[k] = d->vol_shape[k];
+    g->gg.vs[k] = d->voxel_size[k];
+    uint32_t bits;
+    const float fn = (float)d->vol_shape[k];
+    memcpy(&bits, &fn, 4);
+    bits -= 1;  // largest float below n_k (n_k >= 1)
+    memcpy(&g->gg.hi[k], &bits, 4);
+  }
+  g->gg.beam = d->beam;
+  g->n_views = d->n_views;
+  g->n_u = d->n_u;
+  g->n_v = d->n_v;
+  g->beam = d->beam;
+  g->weight = d->weight;
+  for (size_t v = 0; v < nv; ++v) {
+    const double* w = d->views + 12 * v;
+    double* o = g->views_grid.data() + 12 * v;
+    for (int k = 0; k < 3; ++k) {
+      // points -> grid: (w - c) / h + (n - 1) / 2 ; directions -> grid: w / h
+      if (d->beam == GJP_CONE)
+        o[k] = (w[k] - g->ctr[k]) / g->vs[k] + (double)(g->n[k] - 1) * 0.5;
+      else
+        o[k] = w[k] / g->vs[k];
+      o[3 + k] = (w[3 + k] - g->ctr[k]) / g->vs[k] + (double)(g->n[k] - 1) * 0.5;
+      o[6 + k] = w[6 + k] / g->vs[k];
+      o[9 + k] = w[9 + k] / g->vs[k];
+    }
+    detector_projection(o, d->beam, g->proj.data() + 12 * v);
+  }
+  *out = g.release();
+  return GJP_OK;
+}
+
+static void invalidate_plans(uint64_t id);
+
+extern "C" gjp_status gjp_destroy_geometry(gjp_geometry* g) {
+  if (!g) return GJP_OK;
+  invalidate_plans(g->id);
+  bool on_device = false;
+  for (int dvc = 0; dvc < gjp_geometry::kMaxDev; ++dvc) on_device |= (g->dev[dvc].views != nullptr);
+  if (on_device) {  // no HIP call at all for a geometry that never reached a device
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (int dvc = 0; dvc < gjp_geometry::kMaxDev; ++dvc) {
+      if (!g->dev[dvc].views) continue;
+      (void)hipSetDevice(dvc);
+      (void)hipFree(g->dev[dvc].views);
+      (void)hipFree(g->dev[dvc].proj);
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+  }
+  delete g;
+  return GJP_OK;
+}
+
+int gjp::geometry_device(const gjp_geometry* g, const double** views, const float** proj) {
+  int dvc = 0;
+  hipError_t e = hipGetDevice(&dvc);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dvc < 0 || dvc >= gjp_geometry::kMaxDev) return fail(GJP_EUNSUPPORTED, "device index");
+  std::lock_guard<std::mutex> lk(g->mu);
+  gjp_geometry::Dev& D = g->dev[dvc];
+  if (!D.views) {
+    const size_t nb = g->views_grid.size() * sizeof(double);
+    const size_t pb = g->proj.size() * sizeof(float);
+    double* dv = nullptr;
+    float* dp = nullptr;
+    e = hipMalloc(&dv, nb);
+    if (e != hipSuccess) return hip_fail(e, "geometry upload (views)");
+    e = hipMalloc(&dp, pb);
+    if (e != hipSuccess) {
+      (void)hipFree(dv);
+      return hip_fail(e, "geometry upload (projection)");
+    }
+    e = hipMemcpy(dv, g->views_grid.data(), nb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dp, g->proj.data(), pb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dv);
+      (void)hipFree(dp);
+      return hip_fail(e, "geometry upload (copy)");
+    }
+    D.views = dv;
+    D.proj = dp;
+  }
+  *views = D.views;
+  *proj = D.proj;
+  return GJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sample count (host, same double-precision setup as the kernels)
+// ---------------------------------------------------------------------------
+extern "C" gjp_status gjp_count_samples(const gjp_geometry* g, uint64_t* out) {
+  if (!g || !out) return fail(GJP_EINVAL, "gjp_count_samples: null pointer");
+  const long long n_rays = (long long)g->n_views * g->n_u * g->n_v;
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt == 0) nt = 1;
+  if (nt > 64) nt = 64;
+  if (n_rays < 65536) nt = 1;
+  std::vector<uint64_t> part(nt, 0);
+  auto work = [&](unsigned t) {
+    uint64_t acc = 0;
+    const long long per_view = (long long)g->n_u * g->n_v;
+    for (long long r = t; r < n_rays; r += nt) {
+      const int view = (int)(r / per_view);
+      const long long rem = r - (long long)view * per_view;
+      gjp::RaySetup R;
+      gjp::ray_setup(g->views_grid.data() + 12 * (size_t)view, g->gg, (int)(rem / g->n_v),
+                     (int)(rem % g->n_v), R);
+      acc += (uint64_t)(R.i1 - R.i0);
+    }
+    part[t] = acc;
+  };
+  if (nt == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
+  uint64_t total = 0;
+  for (auto p : part) total += p;
+  *out = total;
+  return GJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stream-ordered scratch
+// ---------------------------------------------------------------------------
+static std::once_flag g_pool_once[gjp_geometry::kMaxDev];
+
+static void keep_pool_memory(int dvc) {
+  if (dvc < 0 || dvc >= gjp_geometry::kMaxDev) return;
+  std::call_once(g_pool_once[dvc], [dvc]() {
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dvc) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+}
+
+static hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s) {
+  int dvc = 0;
+  (void)hipGetDevice(&dvc);
+  keep_pool_memory(dvc);
+  return hipMallocAsync(p, bytes, s);
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, FwdTile> g_tune;
+
+std::string tune_key(const gjp_geometry* g, int dtype) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%d,%d,%d|%d,%d,%d|%d,%d,%d", g->n[0], g->n[1], g->n[2],
+           g->n_views, g->n_u, g->n_v, g->beam, g->weight, dtype);
+  return buf;
+}
+
+FwdTile tile_for(const gjp_geometry* g, int dtype) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(g, dtype));
+  if (it != g_tune.end()) return it->second;
+  return FwdTile();
+}
+
+long long padded_elems(const int* n) {
+  return (long long)(n[0] + 2) * (long long)(n[1] + 2) * (long long)(n[2] + 2);
+}
+
+void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* padded,
+                   float* sino, const FwdTile& tile, FwdArgs& a) {
+  const long long p2 = g->n[2] + 2, p1 = g->n[1] + 2;
+  a.S1 = p2;
+  a.S0 = p1 * p2;
+  a.G = g->gg;
+  a.views = d_views;
+  a.sino = sino;
+  a.n_u = g->n_u;
+  a.n_v = g->n_v;
+  a.tile_v_log2 = tile.tile_v_log2;
+  a.remap = tile.remap;
+  const int tile_v = 1 << tile.tile_v_log2;
+  const int tile_u = 256 >> tile.tile_v_log2;
+  a.tiles_v = (g->n_v + tile_v - 1) / tile_v;
+  a.tiles_u = (g->n_u + tile_u - 1) / tile_u;
+  a.tiles_per_view = a.tiles_v * a.tiles_u;
+  a.vol = padded;
+}
+
+const void* padded_origin(const void* padded, int dtype, const FwdArgs& a) {
+  const size_t es = gjp::dtype_size(dtype);
+  return static_cast<const char*>(padded) + (size_t)(a.S0 + a.S1 + 1) * es;
+}
+
+gjp_status validate_fwd(const gjp_geometry* g, const void* d_vol, int32_t dtype,
+                        const float* d_sino) {
+  if (!g) return fail(GJP_EINVAL, "forward: geometry is null");
+  if (!d_vol || !d_sino) return fail(GJP_EINVAL, "forward: null device pointer");
+  if (dtype != GJP_F32 && dtype != GJP_BF16 && dtype != GJP_F16)
+    return fail(GJP_EINVAL, "forward: unknown volume dtype");
+  if (((uintptr_t)d_vol) % gjp::dtype_size(dtype) != 0 || ((uintptr_t)d_sino) % 4 != 0)
+    return fail(GJP_EINVAL, "forward: misaligned pointer");
+  return GJP_OK;
+}
+
+gjp_status forward_with_tile(const gjp_geometry* g, const void* d_vol, int32_t dtype,
+                             float* d_sino, hipStream_t s, const FwdTile& tile) {
+  const double* d_views = nullptr;
+  const float* d_proj = nullptr;
+  int st = gjp::geometry_device(g, &d_views, &d_proj);
+  if (st != GJP_OK) return (gjp_status)st;
+  const long long pe = padded_elems(g->n);
+  const size_t bytes = (size_t)pe * gjp::dtype_size(dtype);
+  void* padded = nullptr;
+  GJP_HIP(scratch_alloc(&padded, bytes, s), "forward: padded volume");
+  FwdArgs a;
+  fill_fwd_args(g, d_views, nullptr, d_sino, tile, a);
+  a.vol = padded_origin(padded, dtype, a);
+  st = gjp::launch_pad(d_vol, padded, dtype, g->n, s);
+  if (st == GJP_OK)
+    st = gjp::launch_forward(a, dtype, g->weight, pe >= (1ll << 31), g->n_views, s);
+  const hipError_t fe = hipFreeAsync(padded, s);
+  if (st != GJP_OK) return (gjp_status)st;
+  if (fe != hipSuccess) return hip_fail(fe, "forward: free padded volume");
+  return GJP_OK;
+}
+}  // namespace
+
+extern "C" gjp_status gjp_forward_project(const gjp_geometry* g, const void* d_vol,
+                                          int32_t vol_dtype, float* d_sino, void* stream) {
+  gjp_status st = validate_fwd(g, d_vol, vol_dtype, d_sino);
+  if (st != GJP_OK) return st;
+  return forward_with_tile(g, d_vol, vol_dtype, d_sino, (hipStream_t)stream,
+                           tile_for(g, vol_dtype));
+}
+
+extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_vol,
+                                           int32_t vol_dtype, float* d_sino, void* stream,
+                                           int32_t* tile_v_out) {
+  gjp_status st = validate_fwd(g, d_vol, vol_dtype, d_sino);
+  if (st != GJP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  GJP_HIP(hipEventCreate(&e0), "autotune event");
+  GJP_HIP(hipEventCreate(&e1), "autotune event");
+  FwdTile best;
+  float best_ms = 3.0e38f;
+  for (int k : {6, 5, 4}) {
+    for (int remap : {1, 0}) {
+      FwdTile t;
+      t.tile_v_log2 = k;
+      t.remap = remap;
+      st = forward_with_tile(g, d_vol, vol_dtype, d_sino, s, t);  // warm-up
+      if (st != GJP_OK) break;
+      GJP_HIP(hipEventRecord(e0, s), "autotune record");
+      const int reps = 3;
+      for (int r = 0; r < reps && st == GJP_OK; ++r)
+        st = forward_with_tile(g, d_vol, vol_dtype, d_sino, s, t);
+      GJP_HIP(hipEventRecord(e1, s), "autotune record");
+      GJP_HIP(hipEventSynchronize(e1), "autotune sync");
+      if (st != GJP_OK) break;
+      float ms = 0.0f;
+      GJP_HIP(hipEventElapsedTime(&ms, e0, e1), "autotune elapsed");
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+    if (st != GJP_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GJP_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(g, vol_dtype)] = best;
+  }
+  if (tile_v_out) *tile_v_out = 1 << best.tile_v_log2;
+  return GJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sino, float* d_vol,
+                                       void* stream) {
+  if (!g) return fail(GJP_EINVAL, "back_project: geometry is null");
+  if (!d_sino || !d_vol) return fail(GJP_EINVAL, "back_project: null device pointer");
+  if (((uintptr_t)d_sino) % 4 != 0 || ((uintptr_t)d_vol) % 4 != 0)
+    return fail(GJP_EINVAL, "back_project: misaligned pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const double* d_views = nullptr;
+  const float* d_proj = nullptr;
+  int st = gjp::geometry_device(g, &d_views, &d_proj);
+  if (st != GJP_OK) return (gjp_status)st;
+  const size_t per_view = (size_t)g->n_u * g->n_v;
+  const size_t entry = 2 * sizeof(float4);
+  const size_t budget = (size_t)512 << 20;
+  long long chunk = (long long)(budget / (per_view * entry));
+  if (chunk < 1) chunk = 1;
+  if (chunk > g->n_views) chunk = g->n_views;
+  void* table = nullptr;
+  void* mask = nullptr;
+  GJP_HIP(scratch_alloc(&table, (size_t)chunk * per_view * entry, s), "back_project: table");
+  hipError_t e = scratch_alloc(&mask, (size_t)chunk * sizeof(int), s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(table, s);
+    return hip_fail(e, "back_project: mask");
+  }
+  for (int v0 = 0; v0 < g->n_views && st == GJP_OK; v0 += (int)chunk) {
+    const int nc = (int)std::min<long long>(chunk, g->n_views - v0);
+    st = gjp::launch_zero_ints(static_cast<int*>(mask), nc, s);
+    if (st == GJP_OK)
+      st = gjp::launch_adjoint_table(g, d_views, d_sino, v0, nc, static_cast<float4*>(table),
+                                     static_cast<int*>(mask), s);
+    if (st == GJP_OK)
+      st = gjp::launch_adjoint_gather(g, d_proj, static_cast<const float4*>(table),
+                                      static_cast<const int*>(mask), v0, nc, v0 > 0, d_vol, s);
+  }
+  const hipError_t f1 = hipFreeAsync(table, s);
+  const hipError_t f2 = hipFreeAsync(mask, s);
+  if (st != GJP_OK) return (gjp_status)st;
+  if (f1 != hipSuccess) return hip_fail(f1, "back_project: free table");
+  if (f2 != hipSuccess) return hip_fail(f2, "back_project: free mask");
+  return GJP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched forward: plan = instance descriptors, work list, queue, graph
+// ---------------------------------------------------------------------------
+namespace {
+struct BatchPlan {
+  std::vector<uint64_t> ids;
+  std::vector<int> dtypes;
+  int device = 0;
+  std::vector<BatchInst> host;  // descriptors without per-call pointers
+  BatchInst* d_insts = nullptr;
+  uint2* d_items = nullptr;
+  int* d_counter = nullptr;
+  void* padded_all = nullptr;
+  int n_items = 0;
+  int grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BatchInst* staging = nullptr;  // pinned
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  std::mutex mu;
+
+  ~BatchPlan() {
+    if (staged) {
+      if (staged_pending) (void)hipEventSynchronize(staged);
+      (void)hipEventDestroy(staged);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    if (d_insts) (void)hipFree(d_insts);
+    if (d_items) (void)hipFree(d_items);
+    if (d_counter) (void)hipFree(d_counter);
+    if (padded_all) (void)hipFree(padded_all);
+    if (staging) (void)hipHostFree(staging);
+    if (cur >= 0) (void)hipSetDevice(cur);
+  }
+};
+
+std::mutex g_plan_mu;
+std::map<std::string, std::shared_ptr<BatchPlan>> g_plans;
+
+std::string plan_key(int n, const gjp_geometry* const* g, const int32_t* dtypes, int dvc) {
+  std::string k = std::to_string(dvc);
+  for (int i = 0; i < n; ++i) {
+    k += "|" + std::to_string(g[i]->id) + ":" + std::to_string(dtypes[i]);
+    const FwdTile t = tile_for(g[i], dtypes[i]);
+    k += ":" + std::to_string(t.tile_v_log2);
+  }
+  return k;
+}
+
+gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes, int dvc,
+                      std::shared_ptr<BatchPlan>& out) {
+  auto P = std::make_shared<BatchPlan>();
+  P->device = dvc;
+  P->host.resize(n);
+  size_t pad_bytes = 0;
+  std::vector<size_t> pad_off(n);
+  for (int i = 0; i < n; ++i) {
+    P->ids.push_back(g[i]->id);
+    P->dtypes.push_back(dtypes[i]);
+    const long long pe = padded_elems(g[i]->n);
+    pad_off[i] = pad_bytes;
+    pad_bytes += ((size_t)pe * gjp::dtype_size(dtypes[i]) + 255) & ~(size_t)255;
+  }
+  GJP_HIP(hipMalloc(&P->padded_all, pad_bytes), "batched: padded volumes");
+  // work items: instances ordered by cost per item (longest first), then view, tile
+  struct InstCost {
+    int inst;
+    double cost;
+  };
+  std::vector<InstCost> order;
+  long long total_items = 0;
+  for (int i = 0; i < n; ++i) {
+    const double* d_views = nullptr;
+    const float* d_proj = nullptr;
+    int st = gjp::geometry_device(g[i], &d_views, &d_proj);
+    if (st != GJP_OK) return (gjp_status)st;
+    BatchInst& I = P->host[i];
+    memset(&I, 0, sizeof(I));
+    const FwdTile tile = tile_for(g[i], dtypes[i]);
+    FwdTile t2 = tile;
+    t2.remap = 0;
+    fill_fwd_args(g[i], d_views, nullptr, nullptr, t2, I.a);
+    I.padded = static_cast<char*>(P->padded_all) + pad_off[i];
+    I.a.vol = padded_origin(I.padded, dtypes[i], I.a);
+    I.n_views = g[i]->n_views;
+    I.dtype = dtypes[i];
+    I.weight = g[i]->weight;
+    I.padded_elems = padded_elems(g[i]->n);
+    I.idx64 = I.padded_elems >= (1ll << 31) ? 1 : 0;
+    const int tile_rays = 256;
+    const double per_item = (double)tile_rays * std::max(g[i]->n[0], std::max(g[i]->n[1], g[i]->n[2]));
+    order.push_back({i, per_item});
+    total_items += (long long)I.n_views * I.a.tiles_per_view;
+  }
+  if (total_items > (1ll << 31) - 1) return fail(GJP_EUNSUPPORTED, "batched: too many work items");
+  std::stable_sort(order.begin(), order.end(),
+                   [](const InstCost& x, const InstCost& y) { return x.cost > y.cost; });
+  std::vector<uint2> items;
+  try {
+    items.reserve((size_t)total_items);
+  } catch (...) {
+    return fail(GJP_ENOMEM, "batched: work list");
+  }
+  for (const auto& oc : order) {
+    const BatchInst& I = P->host[oc.inst];
+    for (int v = 0; v < I.n_views; ++v)
+      for (int t = 0; t < I.a.tiles_per_view; ++t)
+        items.push_back(make_uint2((uint32_t)oc.inst | ((uint32_t)v << 12), (uint32_t)t));
+  }
+  P->n_items = (int)items.size();
+  GJP_HIP(hipMalloc(&P->d_items, std::max<size_t>(1, items.size()) * sizeof(uint2)),
+          "batched: items");
+  GJP_HIP(hipMemcpy(P->d_items, items.data(), items.size() * sizeof(uint2),
+                    hipMemcpyHostToDevice),
+          "batched: items copy");
+  GJP_HIP(hipMalloc(&P->d_insts, (size_t)n * sizeof(BatchInst)), "batched: descriptors");
+  GJP_HIP(hipMalloc(&P->d_counter, sizeof(int)), "batched: queue");
+  GJP_HIP(hipHostMalloc(&P->staging, (size_t)n * sizeof(BatchInst), 0), "batched: staging");
+  GJP_HIP(hipEventCreateWithFlags(&P->staged, hipEventDisableTiming), "batched: event");
+  P->grid = gjp::batched_grid_size();
+  // capture pad + queue reset + persistent kernel once
+  hipStream_t cap;
+  GJP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "batched: capture stream");
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  int st = GJP_OK;
+  if (e == hipSuccess) {
+    st = gjp::launch_batched_pad(P->d_insts, n, cap);
+    if (st == GJP_OK) st = gjp::launch_reset_counter(P->d_counter, cap);
+    if (st == GJP_OK)
+      st = gjp::launch_batched_forward(P->d_insts, P->d_items, P->n_items, P->d_counter,
+                                       P->grid, cap);
+    const hipError_t e2 = hipStreamEndCapture(cap, &P->graph);
+    if (e2 != hipSuccess && st == GJP_OK) st = hip_fail(e2, "batched: end capture");
+  } else {
+    st = hip_fail(e, "batched: begin capture");
+  }
+  (void)hipStreamDestroy(cap);
+  if (st != GJP_OK) return (gjp_status)st;
+  GJP_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0), "batched: instantiate");
+  out = P;
+  return GJP_OK;
+}
+}  // namespace
+
+static void invalidate_plans(uint64_t id) {
+  std::vector<std::shared_ptr<BatchPlan>> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+      if (std::find(it->second->ids.begin(), it->second->ids.end(), id) !=
+          it->second->ids.end()) {
+        drop.push_back(it->second);
+        it = g_plans.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  drop.clear();
+}
+
+extern "C" gjp_status gjp_forward_project_batched(int32_t n, const gjp_geometry* const* g,
+                                                  const void* const* d_vols,
+                                                  const int32_t* dtypes, float* const* d_sinos,
+                                                  void* stream) {
+  if (n <= 0 || n > 4096) return fail(GJP_EINVAL, "batched: n must be in [1, 4096]");
+  if (!g || !d_vols || !dtypes || !d_sinos) return fail(GJP_EINVAL, "batched: null array");
+  for (int i = 0; i < n; ++i) {
+    gjp_status st = validate_fwd(g[i], d_vols[i], dtypes[i], d_sinos[i]);
+    if (st != GJP_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int dvc = 0;
+  GJP_HIP(hipGetDevice(&dvc), "hipGetDevice");
+  const std::string key = plan_key(n, g, dtypes, dvc);
+  std::shared_ptr<BatchPlan> P;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) P = it->second;
+  }
+  if (!P) {
+    gjp_status st = build_plan(n, g, dtypes, dvc, P);
+    if (st != GJP_OK) return st;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plans.size() >= 8) g_plans.erase(g_plans.begin());
+    g_plans[key] = P;
+  }
+  std::lock_guard<std::mutex> lk(P->mu);
+  if (P->staged_pending) GJP_HIP(hipEventSynchronize(P->staged), "batched: staging wait");
+  for (int i = 0; i < n; ++i) {
+    P->staging[i] = P->host[i];
+    P->staging[i].src = d_vols[i];
+    P->staging[i].a.sino = d_sinos[i];
+  }
+  GJP_HIP(hipMemcpyAsync(P->d_insts, P->staging, (size_t)n * sizeof(BatchInst),
+                         hipMemcpyHostToDevice, s),
+          "batched: descriptor upload");
+  GJP_HIP(hipEventRecord(P->staged, s), "batched: staging event");
+  P->staged_pending = true;
+  gjp::TimedLaunch t = gjp::timing_begin("batched", s);
+  GJP_HIP(hipGraphLaunch(P->exec, s), "batched: graph launch");
+  gjp::timing_end("batched", t, s);
+  return GJP_OK;
+}

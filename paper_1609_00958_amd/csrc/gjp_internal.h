@@ -1,0 +1,100 @@
+// gjp_internal.h -- host-side structures shared by the C ABI and the kernel
+// launchers. Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gjp_ray.h"
+
+struct gjp_geometry {
+  uint64_t id;                     // unique per handle (never reused)
+  int n[3];
+  double vs[3];
+  double ctr[3];
+  int n_views, n_u, n_v;
+  int beam, weight;
+  std::vector<double> views_world;  // as given
+  std::vector<double> views_grid;   // n_views x 12, grid units
+  std::vector<float> proj;          // n_views x 12: detector projection rows (u, v, w)
+  gjp::GridGeom gg;
+
+  // device copies, per device (created on first use)
+  struct Dev {
+    double* views = nullptr;
+    float* proj = nullptr;
+  };
+  static constexpr int kMaxDev = 64;
+  mutable std::mutex mu;
+  mutable Dev dev[kMaxDev];
+};
+
+namespace gjp {
+
+// Status plumbing (defined in gjp_api.cpp).
+int set_error(int status, const std::string& msg);
+
+// Kernel timing registry (defined in gjp_api.cpp).
+struct TimedLaunch {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool on = false;
+};
+TimedLaunch timing_begin(const char* name, hipStream_t s);
+void timing_end(const char* name, TimedLaunch& t, hipStream_t s);
+
+// Launch configuration of the forward kernel.
+struct FwdTile {
+  int tile_v_log2 = 6;  // detector pixels along v per wavefront row (64, 32, 16)
+  int remap = 1;        // 1: contiguous tile ranges per XCD
+};
+
+// Arguments of one forward launch (one volume, a range of views).
+struct FwdArgs {
+  const void* vol;      // padded volume, element (1,1,1) of the padded array
+  float* sino;          // sinogram of the whole geometry
+  const double* views;  // device, n_views x 12 grid units
+  GridGeom G;
+  long long S0, S1;     // padded strides in elements
+  int n_u, n_v;
+  int tile_v_log2;
+  int tiles_v, tiles_u, tiles_per_view;
+  int remap;
+};
+
+// Device views of a geometry on the current device (uploads on first use).
+int geometry_device(const gjp_geometry* g, const double** views, const float** proj);
+
+// Launchers (gjp_kernels.hip). Return a gjp_status.
+int launch_pad(const void* src, void* dst, int dtype, const int n[3], hipStream_t s);
+int launch_zero_ints(int* p, int n, hipStream_t s);
+int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,
+                   hipStream_t s);
+int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,
+                         int view0, int n_chunk, float4* table, int* mask, hipStream_t s);
+int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
+                          const int* mask, int view0, int n_chunk, bool accumulate,
+                          float* vol, hipStream_t s);
+
+// Batched forward (gjp_batched.cpp / gjp_kernels.hip).
+struct BatchInst {
+  FwdArgs a;
+  const void* src;      // caller volume (unpadded)
+  void* padded;         // plan-owned padded copy
+  int n_views;
+  int dtype, weight, idx64;
+  long long padded_elems;
+};
+int launch_batched_pad(const BatchInst* d_insts, int n_inst, hipStream_t s);
+int launch_reset_counter(int* counter, hipStream_t s);
+int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
+                           int* counter, int grid, hipStream_t s);
+int batched_grid_size();
+
+size_t dtype_size(int dtype);
+
+}  // namespace gjp

@@ -1,0 +1,493 @@
+// gjp_kernels.hip -- gfx950 kernels of the generalized Joseph projector.
+//
+// Forward (Algorithm 1): one lane per detector pixel. A 256-thread workgroup
+// covers a tile of (64 >> k) x (4 << k) pixels; within a wavefront the fast
+// lane index runs along detector v, the direction parallel to the rotation
+// axis and to the fastest volume index n2. For a circular trajectory the
+// driving axis is then 0 or 1 (never the fastest index, as the paper's
+// Algorithm 1 caption recommends for cache efficiency), the 64 lanes of a
+// wavefront share the same transverse row on every plane, and the two row
+// reads of a sample are contiguous voxel pairs (z, z+1) fetched as one 8-byte
+// (FP32) or 4-byte (16-bit) load. The volume is read from a zero-padded copy
+// (one voxel on every side), so the sampling loop has no bounds tests.
+//
+// Adjoint: exact transpose of the forward. A table pass stores, per ray of a
+// chunk of views, the setup the forward computes (driving axis, sample range,
+// single-precision coefficients) and the sinogram value times the step length.
+// A gather pass assigns one lane per voxel (lanes along n2): for each view and
+// each driving axis present in it, the 2x2 in-plane neighbourhood of the voxel
+// is projected onto the detector, and every candidate ray in the resulting
+// pixel box recomputes the forward's weights with the same `sample_axis` code.
+// Each voxel is written once per chunk; no atomic accumulation.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "gjp_internal.h"
+
+namespace gjp {
+
+struct bf16_t {
+  uint16_t bits;
+};
+struct f16_t {
+  uint16_t bits;
+};
+
+typedef float f2a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32a2 __attribute__((aligned(2)));
+
+__device__ __forceinline__ void load_pair(const float* p, float& x0, float& x1) {
+  const f2a4 v = *reinterpret_cast<const f2a4*>(p);
+  x0 = v.x;
+  x1 = v.y;
+}
+__device__ __forceinline__ void load_pair(const bf16_t* p, float& x0, float& x1) {
+  const uint32_t u = *reinterpret_cast<const u32a2*>(p);
+  x0 = __uint_as_float(u << 16);
+  x1 = __uint_as_float(u & 0xffff0000u);
+}
+__device__ __forceinline__ void load_pair(const f16_t* p, float& x0, float& x1) {
+  const uint32_t u = *reinterpret_cast<const u32a2*>(p);
+  x0 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
+  x1 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+}
+__device__ __forceinline__ float load_one(const float* p) { return *p; }
+__device__ __forceinline__ float load_one(const bf16_t* p) {
+  return __uint_as_float((uint32_t)p->bits << 16);
+}
+__device__ __forceinline__ float load_one(const f16_t* p) {
+  return (float)__builtin_bit_cast(_Float16, p->bits);
+}
+
+// Consecutive workgroup ids are dispatched round-robin over the 8 XCDs (each
+// with its own L2); remap so that each XCD runs one contiguous range of tiles.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+  const uint32_t X = 8;
+  const uint32_t q = nb / X, r = nb % X;
+  const uint32_t xcd = b % X, local = b / X;
+  return xcd * q + (xcd < r ? xcd : r) + local;
+}
+
+// ---------------------------------------------------------------------------
+// Zero-padded copy: dst has (n0+2) x (n1+2) x (n2+2) elements.
+// ---------------------------------------------------------------------------
+template <typename E>
+__global__ __launch_bounds__(256) void pad_kernel(const E* __restrict__ src, E* __restrict__ dst,
+                                                  int n0, int n1, int n2) {
+  const int z = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  const int x = blockIdx.z;
+  const int p2 = n2 + 2;
+  if (z >= p2) return;
+  E val = 0;
+  if (x >= 1 && x <= n0 && y >= 1 && y <= n1 && z >= 1 && z <= n2)
+    val = src[((size_t)(x - 1) * n1 + (y - 1)) * n2 + (z - 1)];
+  dst[((size_t)x * (n1 + 2) + y) * p2 + z] = val;
+}
+
+// ---------------------------------------------------------------------------
+// Forward projection of one ray (Algorithm 1).
+// ---------------------------------------------------------------------------
+template <typename T, int WF, bool IDX64>
+__device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv) {
+  using Index = std::conditional_t<IDX64, long long, int>;
+  RaySetup R;
+  ray_setup(a.views + 12 * (size_t)view, a.G, iu, iv, R);
+  const T* __restrict__ base = static_cast<const T*>(a.vol);
+  float acc = 0.0f;
+  float fi = (float)R.i0;
+  if (R.m != 2) {
+    // transverse axes: ta (rows, strided) and 2 (contiguous pairs)
+    const Index Sm = (Index)(R.m == 0 ? a.S0 : a.S1);
+    const Index Sa = (Index)(R.m == 0 ? a.S1 : a.S0);
+    const float hia = (R.m == 0) ? a.G.hi[1] : a.G.hi[0];
+    const float hib = a.G.hi[2];
+    Index off_m = (Index)R.i0 * Sm;
+    for (int i = R.i0; i < R.i1; ++i) {
+      int ia, ib;
+      float wfa, wca, wfb, wcb;
+      sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
+      sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
+      const Index off = off_m + (Index)ia * Sa + (Index)ib;
+      float v00, v01, v10, v11;
+      load_pair(base + off, v00, v01);
+      load_pair(base + off + Sa, v10, v11);
+      acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
+      acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
+      fi += 1.0f;
+      off_m += Sm;
+    }
+  } else {
+    // driving axis 2: both transverse axes strided, four single loads
+    const Index S0 = (Index)a.S0, S1 = (Index)a.S1;
+    const float hia = a.G.hi[0], hib = a.G.hi[1];
+    for (int i = R.i0; i < R.i1; ++i) {
+      int ia, ib;
+      float wfa, wca, wfb, wcb;
+      sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
+      sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
+      const Index off = (Index)i + (Index)ia * S0 + (Index)ib * S1;
+      const float v00 = load_one(base + off);
+      const float v01 = load_one(base + off + S1);
+      const float v10 = load_one(base + off + S0);
+      const float v11 = load_one(base + off + S0 + S1);
+      acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
+      acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
+      fi += 1.0f;
+    }
+  }
+  a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
+}
+
+template <typename T, int WF, bool IDX64>
+__device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
+  const int tu = t / a.tiles_v;
+  const int tv = t - tu * a.tiles_v;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int k = a.tile_v_log2;
+  const int rows = 64 >> k;
+  const int iv = (tv << k) + (lane & ((1 << k) - 1));
+  const int iu = tu * (4 * rows) + wave * rows + (lane >> k);
+  if (iu < a.n_u && iv < a.n_v) fwd_ray<T, WF, IDX64>(a, view, iu, iv);
+}
+
+template <typename T, int WF, bool IDX64>
+__global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
+  uint32_t b = blockIdx.x;
+  if (a.remap) b = xcd_remap(b, gridDim.x);
+  const int view = (int)(b / (uint32_t)a.tiles_per_view);
+  const int t = (int)(b - (uint32_t)view * (uint32_t)a.tiles_per_view);
+  fwd_tile<T, WF, IDX64>(a, view, t);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint pass 1: per-ray table for views [view0, view0 + n_chunk).
+// Entry (two float4): {m | i0 << 2 | i1 << 17, ca, ga, cb}, {gb, y * scale, 0, 0}.
+// mask[c] collects the driving axes that have samples in view view0 + c.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict__ views,
+                                                        const GridGeom G,
+                                                        const float* __restrict__ sino, int n_u,
+                                                        int n_v, int view0, long long n_rays,
+                                                        float4* __restrict__ table,
+                                                        int* __restrict__ mask) {
+  const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long per_view = (long long)n_u * n_v;
+  int bits = 0;
+  int cv = 0;
+  if (r < n_rays) {
+    cv = (int)(r / per_view);
+    const long long rem = r - (long long)cv * per_view;
+    const int iu = (int)(rem / n_v);
+    const int iv = (int)(rem - (long long)iu * n_v);
+    RaySetup R;
+    ray_setup(views + 12 * (size_t)(view0 + cv), G, iu, iv, R);
+    const float y = sino[(size_t)(view0 + cv) * per_view + rem];
+    const uint32_t mr = (uint32_t)R.m | ((uint32_t)R.i0 << 2) | ((uint32_t)R.i1 << 17);
+    table[2 * r] = make_float4(__uint_as_float(mr), R.ca, R.ga, R.cb);
+    table[2 * r + 1] = make_float4(R.gb, y * R.scale, 0.0f, 0.0f);
+    if (R.i1 > R.i0) bits = 1 << R.m;
+  }
+  // one atomicOr per (wavefront, view) with samples
+  uint64_t pending = __ballot(bits != 0);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int lcv = __shfl(cv, leader);
+    const bool same = (bits != 0) && (cv == lcv);
+    const uint64_t grp = __ballot(same);
+    int orbits = 0;
+    if (__ballot(same && (bits & 1))) orbits |= 1;
+    if (__ballot(same && (bits & 2))) orbits |= 2;
+    if (__ballot(same && (bits & 4))) orbits |= 4;
+    if ((int)(threadIdx.x & 63) == leader) atomicOr(&mask[lcv], orbits);
+    pending &= ~grp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint pass 2: voxel-driven gather over the chunk's views.
+// proj: per view 12 floats, rows (u, v, w) of the map from a grid point q to
+// homogeneous detector coordinates: u = (A_u . q + b_u) / (A_w . q + b_w).
+// ---------------------------------------------------------------------------
+template <int WF>
+__global__ __launch_bounds__(256) void adj_gather_kernel(
+    const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
+    const float4* __restrict__ table, const int* __restrict__ mask, int view0, int n_chunk,
+    int accumulate, float* __restrict__ vol) {
+  const int z = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int x = blockIdx.z;
+  if (z >= G.n[2] || y >= G.n[1]) return;
+  const float fV[3] = {(float)x, (float)y, (float)z};
+  const size_t per_view = (size_t)n_u * n_v;
+  const float e = 1.002f;     // widened neighbourhood (voxels)
+  const float margin = 0.05f; // widened pixel box (pixels)
+  float acc = 0.0f;
+  for (int c = 0; c < n_chunk; ++c) {
+    const int mk = mask[c];
+    if (!mk) continue;
+    const float* P = proj + 12 * (size_t)(view0 + c);
+    const float4* T = table + 2 * per_view * (size_t)c;
+    const float pu = __builtin_fmaf(P[0], fV[0], __builtin_fmaf(P[1], fV[1], __builtin_fmaf(P[2], fV[2], P[3])));
+    const float pv = __builtin_fmaf(P[4], fV[0], __builtin_fmaf(P[5], fV[1], __builtin_fmaf(P[6], fV[2], P[7])));
+    const float pw = __builtin_fmaf(P[8], fV[0], __builtin_fmaf(P[9], fV[1], __builtin_fmaf(P[10], fV[2], P[11])));
+    for (int m = 0; m < 3; ++m) {
+      if (!(mk & (1 << m))) continue;
+      const int ta = (m == 0) ? 1 : 0;
+      const int tb = (m == 2) ? 1 : 2;
+      const int plane = (m == 0) ? x : ((m == 1) ? y : z);
+      const int Va = (ta == 0) ? x : y;
+      const int Vb = (tb == 1) ? y : z;
+      const float hia = (ta == 0) ? G.hi[0] : G.hi[1];
+      const float hib = (tb == 1) ? G.hi[1] : G.hi[2];
+      // candidate pixel box: image of the in-plane square V +- e (axes ta, tb)
+      const float ua = P[ta], va = P[4 + ta], wa = P[8 + ta];
+      const float ub = P[tb], vb = P[4 + tb], wb = P[8 + tb];
+      float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
+      bool full = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float sa = (q & 1) ? e : -e;
+        const float sb = (q & 2) ? e : -e;
+        const float cu = __builtin_fmaf(sa, ua, __builtin_fmaf(sb, ub, pu));
+        const float cvv = __builtin_fmaf(sa, va, __builtin_fmaf(sb, vb, pv));
+        const float cw = __builtin_fmaf(sa, wa, __builtin_fmaf(sb, wb, pw));
+        if (!(cw > 1.0e-6f)) full = true;
+        const float inv = 1.0f / cw;
+        const float uu = cu * inv, vv = cvv * inv;
+        umin = fminf(umin, uu);
+        umax = fmaxf(umax, uu);
+        vmin = fminf(vmin, vv);
+        vmax = fmaxf(vmax, vv);
+      }
+      int iu_lo, iu_hi, iv_lo, iv_hi;
+      if (full) {
+        iu_lo = 0; iu_hi = n_u - 1; iv_lo = 0; iv_hi = n_v - 1;
+      } else {
+        const float ulo = fmaxf(umin - margin, -1.0f), uhi = fminf(umax + margin, (float)n_u);
+        const float vlo = fmaxf(vmin - margin, -1.0f), vhi = fminf(vmax + margin, (float)n_v);
+        iu_lo = max(0, (int)ceilf(ulo));
+        iu_hi = min(n_u - 1, (int)floorf(uhi));
+        iv_lo = max(0, (int)ceilf(vlo));
+        iv_hi = min(n_v - 1, (int)floorf(vhi));
+      }
+      const float fplane = (float)plane;
+      for (int iu = iu_lo; iu <= iu_hi; ++iu) {
+        const float4* row = T + 2 * ((size_t)iu * n_v);
+        for (int iv = iv_lo; iv <= iv_hi; ++iv) {
+          const float4 e0 = row[2 * iv];
+          const uint32_t mr = __float_as_uint(e0.x);
+          const int em = (int)(mr & 3u);
+          const int i0 = (int)((mr >> 2) & 0x7fffu);
+          const int i1 = (int)(mr >> 17);
+          if (em != m || plane < i0 || plane >= i1) continue;
+          int ia;
+          float wfa, wca;
+          sample_axis<WF>(fplane, e0.z, e0.y, hia, ia, wfa, wca);
+          const float wA = (ia == Va) ? wfa : ((ia + 1 == Va) ? wca : 0.0f);
+          const float4 e1 = row[2 * iv + 1];
+          int ib;
+          float wfb, wcb;
+          sample_axis<WF>(fplane, e1.x, e0.w, hib, ib, wfb, wcb);
+          const float wB = (ib == Vb) ? wfb : ((ib + 1 == Vb) ? wcb : 0.0f);
+          acc = __builtin_fmaf(e1.y, wA * wB, acc);
+        }
+      }
+    }
+  }
+  float* out = vol + ((size_t)x * G.n[1] + y) * G.n[2] + z;
+  *out = accumulate ? (*out + acc) : acc;
+}
+
+// ---------------------------------------------------------------------------
+// Batched forward: zero-padded copies of every instance, queue reset, and a
+// persistent kernel pulling (instance, view, tile) items from a device queue.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void batched_pad_kernel(const BatchInst* __restrict__ insts) {
+  const BatchInst& I = insts[blockIdx.y];
+  const int n0 = I.a.G.n[0], n1 = I.a.G.n[1], n2 = I.a.G.n[2];
+  const long long p2 = n2 + 2, p1 = n1 + 2;
+  const long long total = I.padded_elems;
+  const bool two = (I.dtype != 0);
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (long long)gridDim.x * 256) {
+    const long long z = e % p2;
+    const long long t = e / p2;
+    const long long y = t % p1;
+    const long long x = t / p1;
+    const bool in = x >= 1 && x <= n0 && y >= 1 && y <= n1 && z >= 1 && z <= n2;
+    const long long src = ((x - 1) * n1 + (y - 1)) * (long long)n2 + (z - 1);
+    if (two) {
+      const uint16_t* s = static_cast<const uint16_t*>(I.src);
+      static_cast<uint16_t*>(I.padded)[e] = in ? s[src] : (uint16_t)0;
+    } else {
+      const uint32_t* s = static_cast<const uint32_t*>(I.src);
+      static_cast<uint32_t*>(I.padded)[e] = in ? s[src] : 0u;
+    }
+  }
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void reset_counter_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+template <typename T, int WF>
+__device__ __forceinline__ void batched_item_t(const FwdArgs& a, int idx64, int view, int t) {
+  if (idx64)
+    fwd_tile<T, WF, true>(a, view, t);
+  else
+    fwd_tile<T, WF, false>(a, view, t);
+}
+
+__global__ __launch_bounds__(256) void batched_fwd_kernel(const BatchInst* __restrict__ insts,
+                                                          const uint2* __restrict__ items,
+                                                          int n_items, int* __restrict__ counter) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (item >= n_items) break;
+    const uint2 it = items[item];
+    const int inst = (int)(it.x & 0xfffu);
+    const int view = (int)(it.x >> 12);
+    const int t = (int)it.y;
+    const BatchInst& I = insts[inst];
+    const FwdArgs a = I.a;
+    const int sel = I.dtype * 2 + I.weight;
+    switch (sel) {
+      case 0: batched_item_t<float, W_LINEAR>(a, I.idx64, view, t); break;
+      case 1: batched_item_t<float, W_SPLINE>(a, I.idx64, view, t); break;
+      case 2: batched_item_t<bf16_t, W_LINEAR>(a, I.idx64, view, t); break;
+      case 3: batched_item_t<bf16_t, W_SPLINE>(a, I.idx64, view, t); break;
+      case 4: batched_item_t<f16_t, W_LINEAR>(a, I.idx64, view, t); break;
+      default: batched_item_t<f16_t, W_SPLINE>(a, I.idx64, view, t); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return set_error(-3, std::string(what) + ": " + hipGetErrorString(e));
+  return 0;
+}
+
+size_t dtype_size(int dtype) { return dtype == 0 ? 4 : 2; }
+
+int launch_pad(const void* src, void* dst, int dtype, const int n[3], hipStream_t s) {
+  dim3 grid((unsigned)((n[2] + 2 + 255) / 256), (unsigned)(n[1] + 2), (unsigned)(n[0] + 2));
+  TimedLaunch t = timing_begin("pad", s);
+  if (dtype == 0)
+    pad_kernel<uint32_t><<<grid, 256, 0, s>>>(static_cast<const uint32_t*>(src),
+                                               static_cast<uint32_t*>(dst), n[0], n[1], n[2]);
+  else
+    pad_kernel<uint16_t><<<grid, 256, 0, s>>>(static_cast<const uint16_t*>(src),
+                                               static_cast<uint16_t*>(dst), n[0], n[1], n[2]);
+  timing_end("pad", t, s);
+  return check_launch("pad kernel");
+}
+
+template <typename T, int WF>
+static void launch_fwd_t(const FwdArgs& a, bool idx64, unsigned grid, hipStream_t s) {
+  if (idx64)
+    fwd_kernel<T, WF, true><<<grid, 256, 0, s>>>(a);
+  else
+    fwd_kernel<T, WF, false><<<grid, 256, 0, s>>>(a);
+}
+
+int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,
+                   hipStream_t s) {
+  const unsigned long long nb = (unsigned long long)n_views * (unsigned long long)a.tiles_per_view;
+  if (nb == 0) return 0;
+  if (nb > 0xffffffffull) return set_error(-4, "forward: too many workgroups for one launch");
+  const unsigned grid = (unsigned)nb;
+  TimedLaunch t = timing_begin("forward", s);
+  const int sel = dtype * 2 + weight;
+  switch (sel) {
+    case 0: launch_fwd_t<float, W_LINEAR>(a, idx64, grid, s); break;
+    case 1: launch_fwd_t<float, W_SPLINE>(a, idx64, grid, s); break;
+    case 2: launch_fwd_t<bf16_t, W_LINEAR>(a, idx64, grid, s); break;
+    case 3: launch_fwd_t<bf16_t, W_SPLINE>(a, idx64, grid, s); break;
+    case 4: launch_fwd_t<f16_t, W_LINEAR>(a, idx64, grid, s); break;
+    default: launch_fwd_t<f16_t, W_SPLINE>(a, idx64, grid, s); break;
+  }
+  timing_end("forward", t, s);
+  return check_launch("forward kernel");
+}
+
+int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,
+                         int view0, int n_chunk, float4* table, int* mask, hipStream_t s) {
+  const long long n_rays = (long long)n_chunk * g->n_u * g->n_v;
+  const long long nb = (n_rays + 255) / 256;
+  if (nb > 0xffffffffll) return set_error(-4, "adjoint: view chunk too large");
+  TimedLaunch t = timing_begin("adjoint_table", s);
+  adj_table_kernel<<<(unsigned)nb, 256, 0, s>>>(views, g->gg, sino, g->n_u, g->n_v, view0,
+                                                 n_rays, table, mask);
+  timing_end("adjoint_table", t, s);
+  return check_launch("adjoint table kernel");
+}
+
+int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
+                          const int* mask, int view0, int n_chunk, bool accumulate, float* vol,
+                          hipStream_t s) {
+  dim3 grid((unsigned)((g->n[2] + 63) / 64), (unsigned)((g->n[1] + 3) / 4), (unsigned)g->n[0]);
+  TimedLaunch t = timing_begin("adjoint_gather", s);
+  if (g->weight == W_SPLINE)
+    adj_gather_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
+                                                     view0, n_chunk, accumulate ? 1 : 0, vol);
+  else
+    adj_gather_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
+                                                     view0, n_chunk, accumulate ? 1 : 0, vol);
+  timing_end("adjoint_gather", t, s);
+  return check_launch("adjoint gather kernel");
+}
+
+int launch_batched_pad(const BatchInst* d_insts, int n_inst, hipStream_t s) {
+  dim3 grid(512, (unsigned)n_inst);
+  batched_pad_kernel<<<grid, 256, 0, s>>>(d_insts);
+  return check_launch("batched pad kernel");
+}
+
+int launch_zero_ints(int* p, int n, hipStream_t s) {
+  if (n <= 0) return 0;
+  zero_ints_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+  return check_launch("zero kernel");
+}
+
+int launch_reset_counter(int* counter, hipStream_t s) {
+  reset_counter_kernel<<<1, 64, 0, s>>>(counter);
+  return check_launch("queue reset kernel");
+}
+
+int batched_grid_size() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_fwd_kernel, 256, 0) !=
+          hipSuccess ||
+      per <= 0)
+    per = 4;
+  return cus * per;
+}
+
+int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
+                           int* counter, int grid, hipStream_t s) {
+  batched_fwd_kernel<<<grid, 256, 0, s>>>(d_insts, d_items, n_items, counter);
+  return check_launch("batched forward kernel");
+}
+
+}  // namespace gjp

@@ -1,0 +1,168 @@
+// gjp_ray.h -- per-ray setup and per-sample weights of the generalized Joseph
+// projector, shared by the host sample count and every device kernel.
+//
+// The ray setup (Eqs. 1-5, Algorithm 1 setup) runs in double precision and
+// yields the driving axis, the exact sample range and single-precision
+// coefficients of the two transverse coordinates; the sampling loop
+// (Eqs. 6-13) then runs in single precision. The forward and the adjoint
+// kernels evaluate a sample through the same `sample_axis` function, so the
+// adjoint reproduces the forward's weights bit for bit.
+//
+// This file must be compiled without floating-point contraction
+// (-ffp-contract=off): the driving axis and the sample range decide integer
+// outcomes and have to agree between host and device, operation for
+// operation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define GJP_HD __host__ __device__ __forceinline__
+
+namespace gjp {
+
+enum { W_LINEAR = 0, W_SPLINE = 1 };
+enum { BEAM_CONE = 0, BEAM_PARALLEL = 1 };
+
+// Scan geometry of one volume as the kernels see it (grid units).
+struct GridGeom {
+  int n[3];        // voxels per axis
+  double vs[3];    // voxel size (world units per grid step)
+  float hi[3];     // largest float below n[k]: upper clamp of sample coordinates
+  int beam;
+};
+
+// Result of the per-ray setup.
+struct RaySetup {
+  int m;            // driving axis (Eq. 3)
+  int ta, tb;       // transverse axes, ta < tb
+  int i0, i1;       // sample planes [i0, i1) along m; empty if i0 >= i1
+  float ca, ga;     // p_ta(i) = fma(i, ga, ca)
+  float cb, gb;     // p_tb(i) = fma(i, gb, cb)
+  float scale;      // world-space length of one plane step, || r~ * voxel_size ||
+};
+
+// Sample predicate on one transverse axis: the coordinate of plane i on the
+// line s + (i - s_m) g (Eq. 6 with o = -s_m) lies in the zero-padded domain.
+GJP_HD bool inside_axis(double s_k, double neg_sm, double g_k, int i, int n_k) {
+  const double p = s_k + (neg_sm + (double)i) * g_k;
+  return p > -1.0 && p < (double)n_k;
+}
+
+GJP_HD bool inside_both(const double* s, double neg_sm, const double* g, int a, int b,
+                        const int* n, int i) {
+  return inside_axis(s[a], neg_sm, g[a], i, n[a]) && inside_axis(s[b], neg_sm, g[b], i, n[b]);
+}
+
+// Real interval of planes where axis k stays inside (-1, n_k), widened to
+// integers and clamped to [lo_i, hi_i).
+GJP_HD void axis_interval(double s_k, double s_m, double g_k, int n_k, double& lo, double& hi) {
+  if (g_k == 0.0) {
+    const bool in = s_k > -1.0 && s_k < (double)n_k;
+    lo = in ? -1.0e300 : 1.0e300;
+    hi = in ? 1.0e300 : -1.0e300;
+    return;
+  }
+  const double t0 = s_m + (-1.0 - s_k) / g_k;
+  const double t1 = s_m + ((double)n_k - s_k) / g_k;
+  lo = t0 < t1 ? t0 : t1;
+  hi = t0 < t1 ? t1 : t0;
+}
+
+// Per-ray setup for pixel (iu, iv) of a view given in grid units:
+// v[0..2] = source (cone) or direction (parallel), v[3..5] = det00,
+// v[6..8] = du, v[9..11] = dv.
+GJP_HD void ray_setup(const double* __restrict__ v, const GridGeom& G, int iu, int iv,
+                      RaySetup& R) {
+  double d[3], s[3], r[3];
+  for (int k = 0; k < 3; ++k) d[k] = v[3 + k] + (double)iu * v[6 + k] + (double)iv * v[9 + k];
+  if (G.beam == BEAM_CONE) {
+    for (int k = 0; k < 3; ++k) {
+      s[k] = v[k];
+      r[k] = d[k] - v[k];  // Eq. 2
+    }
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      s[k] = d[k];
+      r[k] = v[k];
+    }
+  }
+  // Eq. 3, ties to the lowest axis
+  int m = 0;
+  if (fabs(r[1]) > fabs(r[m])) m = 1;
+  if (fabs(r[2]) > fabs(r[m])) m = 2;
+  const int a = (m == 0) ? 1 : 0;
+  const int b = (m == 2) ? 1 : 2;
+  R.m = m;
+  R.ta = a;
+  R.tb = b;
+  R.i0 = 0;
+  R.i1 = 0;
+  R.ca = R.ga = R.cb = R.gb = 0.0f;
+  R.scale = 0.0f;
+  if (r[m] == 0.0) return;  // no direction: no samples
+  double g[3];
+  g[a] = r[a] / r[m];  // Eq. 4
+  g[b] = r[b] / r[m];
+  g[m] = 1.0;
+  double q = 0.0;
+  for (int k = 0; k < 3; ++k) q += (g[k] * G.vs[k]) * (g[k] * G.vs[k]);
+  R.scale = (float)sqrt(q);
+  const double neg_sm = -s[m];  // Eq. 5
+  R.ca = (float)(s[a] + neg_sm * g[a]);
+  R.ga = (float)g[a];
+  R.cb = (float)(s[b] + neg_sm * g[b]);
+  R.gb = (float)g[b];
+
+  // Sample range: analytic estimate, then the exact predicate at the ends.
+  // The predicate is monotone in i on each axis, so the samples form one run.
+  const int nm = G.n[m];
+  double lo_a, hi_a, lo_b, hi_b;
+  axis_interval(s[a], s[m], g[a], G.n[a], lo_a, hi_a);
+  axis_interval(s[b], s[m], g[b], G.n[b], lo_b, hi_b);
+  double lo = lo_a > lo_b ? lo_a : lo_b;
+  double hi = hi_a < hi_b ? hi_a : hi_b;
+  lo = lo < -2.0 ? -2.0 : (lo > (double)nm + 1.0 ? (double)nm + 1.0 : lo);
+  hi = hi < -2.0 ? -2.0 : (hi > (double)nm + 1.0 ? (double)nm + 1.0 : hi);
+  int i0 = (int)floor(lo) + 1;
+  int i1 = (int)ceil(hi);
+  i0 = i0 < 0 ? 0 : (i0 > nm ? nm : i0);
+  i1 = i1 < 0 ? 0 : (i1 > nm ? nm : i1);
+  if (i1 < i0) i1 = i0;
+  while (i0 < i1 && !inside_both(s, neg_sm, g, a, b, G.n, i0)) ++i0;
+  while (i0 > 0 && inside_both(s, neg_sm, g, a, b, G.n, i0 - 1)) --i0;
+  if (i1 < i0) i1 = i0;
+  while (i1 > i0 && !inside_both(s, neg_sm, g, a, b, G.n, i1 - 1)) --i1;
+  while (i1 < nm && inside_both(s, neg_sm, g, a, b, G.n, i1)) ++i1;
+  R.i0 = i0;
+  R.i1 = i1;
+}
+
+// Eq. 13 / Eq. 14
+template <int WF>
+__device__ __forceinline__ float weight_fn(float d) {
+  if constexpr (WF == W_SPLINE) {
+    // 1 - 3 d^2 + 2 d^3 = 1 + d^2 (2 d - 3)
+    return __builtin_fmaf(d * d, __builtin_fmaf(2.0f, d, -3.0f), 1.0f);
+  } else {
+    return 1.0f - d;
+  }
+}
+
+// One transverse coordinate of the sample on plane `fi`: position, clamp to
+// the padded domain [-1, n), floor, and the complementary weight pair
+// (Eqs. 10-11). The clamp only acts where single-precision rounding leaves a
+// coordinate outside the double-precision sample range.
+template <int WF>
+__device__ __forceinline__ void sample_axis(float fi, float g, float c, float hi, int& i_fl,
+                                            float& w_fl, float& w_cl) {
+  float p = __builtin_fmaf(fi, g, c);
+  p = __builtin_amdgcn_fmed3f(p, -1.0f, hi);
+  const float f = __builtin_floorf(p);
+  const float d = p - f;
+  w_fl = weight_fn<WF>(d);
+  w_cl = 1.0f - w_fl;
+  i_fl = (int)f;
+}
+
+}  // namespace gjp

@@ -1,0 +1,147 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+validates arguments before touching a device, and its host-side steps (the
+circular trajectories and the double-precision ray setup behind the sample
+count) agree exactly with the oracle. No compute call needs a GPU here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gjp():
+    import paper_1609_00958_amd as m
+    return m
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "gjp.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(gjp_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(gjp):
+    from paper_1609_00958_amd import _lib
+    declared = _declared_functions()
+    assert len(declared) >= 12
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(_lib.EXPORTS)
+
+
+def test_error_paths_without_gpu(gjp):
+    from paper_1609_00958_amd import _lib
+    L = _lib.lib()
+    views = np.zeros((2, 12))
+    views[:, 6] = 1.0
+    views[:, 10] = 1.0
+
+    def desc(**kw):
+        d = _lib.GeometryDesc()
+        for k in range(3):
+            d.vol_shape[k] = kw.get("shape", (8, 8, 8))[k]
+            d.voxel_size[k] = kw.get("vs", 1.0)
+        d.n_views, d.n_u, d.n_v = kw.get("n_views", 2), kw.get("n_u", 4), kw.get("n_v", 4)
+        d.beam = kw.get("beam", 0)
+        v = kw.get("views", views)
+        d.views = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if v is not None else None
+        d.weight = kw.get("weight", 0)
+        d.flags = kw.get("flags", 0)
+        return d, v
+
+    h = ctypes.c_void_p()
+    for kw in ({"shape": (0, 8, 8)}, {"shape": (8, -1, 8)}, {"shape": (8, 8, 40000)},
+               {"vs": 0.0}, {"n_views": 0}, {"n_u": 0}, {"beam": 7}, {"weight": 3},
+               {"flags": 1}, {"views": None}):
+        d, keep = desc(**kw)
+        st = L.gjp_create_geometry(ctypes.byref(d), ctypes.byref(h))
+        assert st == _lib.GJP_EINVAL, kw
+        assert L.gjp_last_error().decode()
+    bad = views.copy()
+    bad[1, 4] = np.nan
+    d, keep = desc(views=bad)
+    assert L.gjp_create_geometry(ctypes.byref(d), ctypes.byref(h)) == _lib.GJP_EINVAL
+    assert b"non-finite" in L.gjp_last_error()
+    assert L.gjp_create_geometry(None, ctypes.byref(h)) == _lib.GJP_EINVAL
+    # projection calls reject null / bad arguments before any GPU work
+    d, keep = desc()
+    assert L.gjp_create_geometry(ctypes.byref(d), ctypes.byref(h)) == _lib.GJP_OK
+    assert L.gjp_forward_project(h, None, 0, None, None) == _lib.GJP_EINVAL
+    assert L.gjp_forward_project(h, 16, 9, 16, None) == _lib.GJP_EINVAL
+    assert L.gjp_forward_project(None, 16, 0, 16, None) == _lib.GJP_EINVAL
+    assert L.gjp_forward_project(h, 18, 0, 16, None) == _lib.GJP_EINVAL  # misaligned
+    assert L.gjp_back_project(h, None, 16, None) == _lib.GJP_EINVAL
+    assert L.gjp_forward_project_batched(0, None, None, None, None, None) == _lib.GJP_EINVAL
+    cnt = ctypes.c_uint64()
+    assert L.gjp_count_samples(None, ctypes.byref(cnt)) == _lib.GJP_EINVAL
+    assert L.gjp_views_circular_cone(0, 1.0, 2.0, 1.0, 1.0, 4, 4, None) == _lib.GJP_EINVAL
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert L.gjp_timing_read(b"forward", ctypes.byref(ms), ctypes.byref(n)) == _lib.GJP_OK
+    assert L.gjp_destroy_geometry(h) == _lib.GJP_OK
+    assert L.gjp_destroy_geometry(None) == _lib.GJP_OK
+    with pytest.raises(gjp.GJPError):
+        gjp.views_parallel(3, 1.0, 1.0, -1, 4)
+
+
+@pytest.mark.parametrize("n_views", [7, 64, 180, 360, 720, 1440])
+def test_trajectories_bitwise_equal_to_oracle(gjp, oracle_mod, n_views):
+    for args in ((256.0, 512.0, 2.0, 2.0, 64, 64), (1024.0, 1536.0, 1.0, 1.0, 384, 384),
+                 (2048.0, 3072.0, 1.0, 1.0, 768, 768)):
+        a = gjp.views_circular_cone(n_views, *args)
+        b = oracle_mod.views_circular_cone(n_views, *args)
+        assert np.array_equal(a, b)
+    a = gjp.views_parallel(n_views, 1.25, 0.75, 64, 32)
+    b = oracle_mod.views_parallel(n_views, 1.25, 0.75, 64, 32)
+    assert np.array_equal(a, b)
+
+
+def test_sample_count_equals_oracle_configs(gjp, oracle_mod):
+    # the host pass runs the kernels' double-precision setup; the oracle counts
+    # its own loop (Algorithm 1 with the in-volume test on every plane)
+    for name in ("c1",):
+        cfg = workloads.config(name)
+        G = gjp.Geometry.from_config(cfg)
+        assert G.count_samples() == oracle_mod.count_samples(oracle_mod.geometry_for(cfg))
+    small = [
+        workloads.WorkloadConfig("p", (20, 24, 18), 30, 40, 28, beam="parallel", pitch_u=0.9,
+                                 pitch_v=0.8),
+        workloads.WorkloadConfig("c", (32, 32, 32), 24, 50, 50, beam="cone", sod=60.0,
+                                 sdd=130.0, pitch_u=1.3, pitch_v=1.3),
+    ]
+    for cfg in small:
+        G = gjp.Geometry.from_config(cfg)
+        assert G.count_samples() == oracle_mod.count_samples(oracle_mod.geometry_for(cfg))
+
+
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+def test_sample_count_equals_oracle_random_geometry(gjp, oracle_mod, beam):
+    shape = (13, 17, 11)
+    n_views, n_u, n_v = 40, 21, 19
+    if beam == "cone":
+        views = workloads.random_cone_views(61, n_views, shape, n_u, n_v)
+        b = oracle_mod.CONE
+    else:
+        views = workloads.random_parallel_views(61, n_views, shape, n_u, n_v)
+        b = oracle_mod.PARALLEL
+    G = gjp.Geometry(shape, views, n_u, n_v, beam=beam)
+    og = oracle_mod.Geometry(shape, views, n_u, n_v, beam=b)
+    assert G.count_samples() == oracle_mod.count_samples(og)
+
+
+def test_sample_count_anisotropic_voxels(gjp, oracle_mod):
+    shape = (16, 12, 20)
+    vs = (0.7, 1.3, 0.9)
+    ctr = (1.5, -2.0, 0.25)
+    views = workloads.random_cone_views(62, 12, shape, 15, 17, voxel_size=vs)
+    views[:, 0:3] += ctr
+    views[:, 3:6] += ctr
+    G = gjp.Geometry(shape, views, 15, 17, voxel_size=vs, center=ctr)
+    og = oracle_mod.Geometry(shape, views, 15, 17, voxel_size=vs, center=ctr)
+    assert G.count_samples() == oracle_mod.count_samples(og)

@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: relative L2 <= 1e-5 for FP32 volumes, <= 5e-3 for 16-bit storage
+against the unrounded volume, and <= 1e-5 against the 16-bit-rounded volume
+(the kernel's own error). Integer outcomes (sample counts) are exact.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import cuda, note, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 5e-3
+
+
+@pytest.fixture(scope="module")
+def gjp():
+    import paper_1609_00958_amd as m
+    return m
+
+
+def _oracle_geom(oracle_mod, G):
+    beam = oracle_mod.CONE if G.beam == 0 else oracle_mod.PARALLEL
+    return oracle_mod.Geometry(G.shape, G.views, G.n_u, G.n_v, beam=beam,
+                               voxel_size=G.voxel_size, center=G.center, weight=G.weight)
+
+
+def _to_dev(a, dev, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    return t if dtype is None else t.to(dtype)
+
+
+# ---------------------------------------------------------------------------
+# forward, small configurations: full sinograms against the oracle
+# ---------------------------------------------------------------------------
+def test_forward_c1_fp32(gjp, oracle_mod):
+    dev = cuda()
+    cfg = workloads.config("c1")
+    vol = workloads.rasterize(cfg.phantom_ellipsoids(), cfg.shape)
+    G = gjp.Geometry.from_config(cfg)
+    note("forward c1 fp32")
+    y = gjp.forward(_to_dev(vol, dev), G).cpu().numpy()
+    want = oracle_mod.forward(oracle_mod.geometry_for(cfg), vol)
+    assert rel_l2(y, want) <= TOL32
+    assert np.abs(y - want).max() <= 1e-4 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+@pytest.mark.parametrize("weight", ["linear", "spline"])
+def test_forward_random_geometry(gjp, oracle_mod, beam, weight):
+    """Random orientations (every driving axis), ragged detector and grid sizes
+    that span several tiles, anisotropic voxels and an offset grid centre."""
+    dev = cuda()
+    shape = (37, 29, 70)
+    vs = (1.0, 1.25, 0.8)
+    ctr = (3.0, -1.5, 2.0)
+    n_views, n_u, n_v = 11, 45, 131
+    gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+    views = gen(71, n_views, shape, n_u, n_v, voxel_size=vs)
+    for k in (0, 3) if beam == "cone" else (3,):
+        views[:, k:k + 3] += ctr
+    G = gjp.Geometry(shape, views, n_u, n_v, beam=beam, voxel_size=vs, center=ctr, weight=weight)
+    og = _oracle_geom(oracle_mod, G)
+    vol = workloads.rasterize(workloads.random_ellipsoids(72, shape, voxel_size=vs), shape,
+                              voxel_size=vs, center=ctr)
+    vol += np.random.default_rng(73).uniform(0, 0.05, size=shape).astype(np.float32)
+    note(f"forward random {beam} {weight}")
+    y = gjp.forward(_to_dev(vol, dev), G).cpu().numpy()
+    want = oracle_mod.forward(og, vol)
+    axes = {oracle_mod.ray_info(og, v, n_u // 2, n_v // 2)[0] for v in range(n_views)}
+    assert len(axes) >= 2
+    assert rel_l2(y, want) <= TOL32
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_forward_16bit_storage(gjp, oracle_mod, dtype):
+    import torch
+    dev = cuda()
+    cfg = workloads.config("c1")
+    vol = workloads.rasterize(cfg.phantom_ellipsoids(), cfg.shape)
+    vol += np.random.default_rng(74).normal(0, 0.01, size=vol.shape).astype(np.float32)
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float16
+    v16 = _to_dev(vol, dev).to(tdt)
+    G = gjp.Geometry.from_config(cfg)
+    note(f"forward c1 {dtype}")
+    y = gjp.forward(v16, G).cpu().numpy()
+    og = oracle_mod.geometry_for(cfg)
+    rounded = v16.float().cpu().numpy()
+    assert rel_l2(y, oracle_mod.forward(og, rounded)) <= TOL32   # kernel error
+    assert rel_l2(y, oracle_mod.forward(og, vol)) <= TOL16       # storage error
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+@pytest.mark.parametrize("weight", ["linear", "spline"])
+def test_adjoint_random_geometry(gjp, oracle_mod, beam, weight):
+    dev = cuda()
+    shape = (23, 31, 66)
+    n_views, n_u, n_v = 9, 40, 75
+    gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+    views = gen(81, n_views, shape, n_u, n_v)
+    G = gjp.Geometry(shape, views, n_u, n_v, beam=beam, weight=weight)
+    og = _oracle_geom(oracle_mod, G)
+    y = np.random.default_rng(82).uniform(0, 1, size=G.sino_shape).astype(np.float32)
+    note(f"adjoint random {beam} {weight}")
+    x = gjp.back(_to_dev(y, dev), G).cpu().numpy()
+    want = oracle_mod.adjoint(og, y)
+    assert rel_l2(x, want) <= TOL32
+
+
+def test_adjoint_c1(gjp, oracle_mod):
+    dev = cuda()
+    cfg = workloads.config("c1")
+    G = gjp.Geometry.from_config(cfg)
+    y = np.random.default_rng(83).normal(size=G.sino_shape).astype(np.float32)
+    note("adjoint c1")
+    x = gjp.back(_to_dev(y, dev), G).cpu().numpy()
+    want = oracle_mod.adjoint(oracle_mod.geometry_for(cfg), y)
+    assert rel_l2(x, want) <= TOL32
+
+
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+def test_dot_product_gpu(gjp, beam):
+    import torch
+    dev = cuda()
+    shape = (40, 36, 52)
+    n_views, n_u, n_v = 13, 57, 61
+    gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+    G = gjp.Geometry(shape, gen(91, n_views, shape, n_u, n_v), n_u, n_v, beam=beam)
+    g = torch.Generator(device="cpu").manual_seed(92)
+    for signed in (False, True):
+        x = torch.rand(shape, generator=g)
+        y = torch.randn(G.sino_shape, generator=g) if signed else torch.rand(G.sino_shape,
+                                                                              generator=g)
+        note(f"dot test {beam} signed={signed}")
+        Ax = gjp.forward(x.to(dev), G).double().cpu()
+        ATy = gjp.back(y.to(dev), G).double().cpu()
+        lhs = float((Ax * y.double()).sum())
+        rhs = float((x.double() * ATy).sum())
+        assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs))
+
+
+def test_deterministic(gjp):
+    import torch
+    dev = cuda()
+    cfg = workloads.config("c1")
+    G = gjp.Geometry.from_config(cfg)
+    x = torch.rand(cfg.shape, generator=torch.Generator().manual_seed(5)).to(dev)
+    note("determinism")
+    a, b = gjp.forward(x, G), gjp.forward(x, G)
+    assert torch.equal(a, b)
+    c, d = gjp.back(a, G), gjp.back(a, G)
+    assert torch.equal(c, d)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_edge_cases(gjp, oracle_mod):
+    dev = cuda()
+    rng = np.random.default_rng(95)
+    cases = [
+        ((1, 1, 1), 3, 1, 1), ((1, 5, 9), 4, 7, 3), ((9, 1, 4), 5, 2, 65), ((2, 3, 130), 3, 65, 1),
+    ]
+    for shape, n_views, n_u, n_v in cases:
+        for beam in ("cone", "parallel"):
+            gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+            G = gjp.Geometry(shape, gen(96, n_views, shape, n_u, n_v), n_u, n_v, beam=beam)
+            og = _oracle_geom(oracle_mod, G)
+            vol = rng.uniform(0, 1, size=shape).astype(np.float32)
+            note(f"edge {shape} {beam} det {n_u}x{n_v}")
+            y = gjp.forward(_to_dev(vol, dev), G).cpu().numpy()
+            want = oracle_mod.forward(og, vol)
+            assert rel_l2(y, want) <= TOL32 or np.abs(want).max() == 0.0
+            ys = rng.uniform(0, 1, size=G.sino_shape).astype(np.float32)
+            x = gjp.back(_to_dev(ys, dev), G).cpu().numpy()
+            assert rel_l2(x, oracle_mod.adjoint(og, ys)) <= TOL32
+    # rays that miss the grid and a degenerate ray (source on the pixel)
+    views = np.zeros((1, 12))
+    views[0, 0:3] = [0.25, 0.5, -0.75]
+    views[0, 3:6] = [0.25, 0.5, -0.75]
+    views[0, 6:9] = [100.0, 0.0, 0.0]
+    views[0, 9:12] = [0.0, 100.0, 0.0]
+    G = gjp.Geometry((6, 6, 6), views, 3, 2)
+    note("edge degenerate")
+    y = gjp.forward(_to_dev(np.ones((6, 6, 6), np.float32), dev), G).cpu().numpy()
+    og = _oracle_geom(oracle_mod, G)
+    np.testing.assert_allclose(y, oracle_mod.forward(og, np.ones((6, 6, 6))), rtol=1e-5,
+                               atol=1e-6)
+    assert y[0, 0, 0] == 0.0
+
+
+def test_tile_shapes_bitwise_identical(gjp):
+    import torch
+    dev = cuda()
+    shape = (48, 40, 56)
+    n_views, n_u, n_v = 7, 77, 90
+    G = gjp.Geometry(shape, workloads.random_cone_views(97, n_views, shape, n_u, n_v), n_u, n_v)
+    x = torch.rand(shape, generator=torch.Generator().manual_seed(98)).to(dev)
+    note("tile shapes")
+    ref = gjp.forward(x, G)
+    tv = gjp.autotune(x, G)
+    assert tv in (64, 32, 16)
+    assert torch.equal(gjp.forward(x, G), ref)
