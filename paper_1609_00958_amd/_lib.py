@@ -56,6 +56,9 @@ def lib():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1609_00958_amd/build.py")
+    # torch supplies device memory and streams; load its HIP runtime first so
+    # that libgjp binds to that same runtime (one HIP/HSA runtime per process).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u64, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                               ctypes.c_double)
