@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the generalized Joseph projector hot path on one MI355X.
+
+One step = one pass of the whole projection path over the synthetic workload
+(default: 256^3 volume of 12 seeded random ellipsoids, 360 cone-beam views
+over 360 degrees, 384 x 384 detector, magnification 1.5):
+  1. differentiable FP32 forward  y = A x        (autograd forward)
+  2. hand-written adjoint         A^T w          (autograd backward)
+  3. BF16-storage forward
+  4. FP16-storage forward
+`value` is ray-samples per second over the whole step (each pass processes the
+workload's exact sample count S). Inputs are resident in HBM before timing.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(cfg, vol_np, target_s: float):
+    """Time the FP64 oracle forward on a bounded random sample of the workload's rays."""
+    import oracle
+    import workloads
+    og = oracle.geometry_for(cfg)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(int(cores), 16))
+    oracle.set_num_threads(cores)
+    # grow a probe until it runs for about a second, then size the sample
+    n_probe = 4000
+    while True:
+        probe = workloads.sample_rays(11, n_probe, cfg.n_views, cfg.n_u, cfg.n_v)
+        t0 = time.perf_counter()
+        _, c = oracle.forward_rays(og, vol_np, probe, with_counts=True)
+        dt = time.perf_counter() - t0
+        if dt >= 1.0 or n_probe >= cfg.n_rays:
+            break
+        n_probe = min(cfg.n_rays, n_probe * 4)
+    rate = max(int(c.sum()), 1) / max(dt, 1e-6)
+    n_rays = int(min(cfg.n_rays, max(4000, target_s * rate / max(c.mean(), 1.0))))
+    rays = workloads.sample_rays(12, n_rays, cfg.n_views, cfg.n_u, cfg.n_v)
+    t0 = time.perf_counter()
+    _, c = oracle.forward_rays(og, vol_np, rays, with_counts=True)
+    dt = time.perf_counter() - t0
+    samples = int(c.sum())
+    return {
+        "value": samples / dt,
+        "unit": "ray-samples/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"FP64 oracle forward of {n_rays} uniformly sampled rays of the workload "
+                  f"({samples} ray-samples, {dt:.1f} s, {cpu_model()})",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--autotune", action="store_true", help="autotune the forward tile first")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: every box in this setup has one GPU and the "
+              "projector is benchmarked on one GPU's share of the work (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1609_00958_amd as gjp
+    import workloads
+
+    dev = torch.device("cuda:0")
+    cfg = workloads.config(args.workload)
+    log(f"workload {cfg.name}: {cfg.shape} grid, {cfg.n_views} views, {cfg.n_u}x{cfg.n_v}")
+    t0 = time.perf_counter()
+    ells = cfg.phantom_ellipsoids()
+    if int(np.prod(cfg.shape)) <= 256 ** 3:
+        vol_np = workloads.rasterize(ells, cfg.shape)
+        x = torch.from_numpy(vol_np).to(dev)
+    else:
+        x = workloads.rasterize_torch(ells, cfg.shape, dev)
+        vol_np = None
+    G = gjp.Geometry.from_config(cfg)
+    S = G.count_samples()
+    log(f"phantom + geometry ready in {time.perf_counter() - t0:.1f} s; S = {S} ray-samples")
+    x_bf16 = x.to(torch.bfloat16)
+    x_f16 = x.to(torch.float16)
+    xr = x.clone().requires_grad_(True)
+    w = torch.rand(G.sino_shape, generator=torch.Generator().manual_seed(3)).to(dev)
+    if args.autotune:
+        for v in (x, x_bf16, x_f16):
+            log(f"autotune {v.dtype}: tile_v = {gjp.autotune(v, G)}")
+    torch.cuda.synchronize()
+
+    def step():
+        xr.grad = None
+        y = gjp.project(xr, G)          # FP32 forward (autograd)
+        y.backward(w)                   # adjoint (hand-written backward)
+        gjp.forward(x_bf16, G)          # BF16 storage
+        gjp.forward(x_f16, G)           # FP16 storage
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gjp.timing_reset()
+    gjp.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gjp.timing_enable(False)
+    kern = {k: gjp.timing_read(k) for k in ("pad", "forward", "adjoint_table", "adjoint_gather")}
+    ms_per_step = 1e3 * elapsed / args.steps
+    samples_per_step = 4 * S
+    value = samples_per_step / (elapsed / args.steps)
+
+    # per-kernel figures (forward launches: f32, bf16, f16 in that order each step)
+    fwd_ms, fwd_n = kern["forward"]
+    gat_ms, gat_n = kern["adjoint_gather"]
+    tab_ms, tab_n = kern["adjoint_table"]
+    # per-dtype forward times: time each dtype separately, outside the timed steps
+    per_dtype = {}
+    for name, v, bps in (("f32", x, 16), ("bf16", x_bf16, 8), ("f16", x_f16, 8)):
+        gjp.timing_reset()
+        gjp.timing_enable(True)
+        for _ in range(3):
+            gjp.forward(v, G)
+        torch.cuda.synchronize()
+        gjp.timing_enable(False)
+        ms, n = gjp.timing_read("forward")
+        avg = ms / max(n, 1)
+        per_dtype[name] = {
+            "ms": avg,
+            "ray_samples_per_s": S / (avg * 1e-3),
+            "alg_GBps": (bps * S + 4 * G.n_views * G.n_u * G.n_v) / (avg * 1e-3) / 1e9,
+        }
+    n_rays = G.n_views * G.n_u * G.n_v
+    n_vox = int(np.prod(cfg.shape))
+    gat_avg = gat_ms / max(gat_n, 1)
+    adj_launches_per_step = max(gat_n // args.steps, 1)
+    adj_ms_step = (gat_ms + tab_ms) / args.steps
+    # algorithmic bytes of one gather launch: 16 B per sample of its view chunk + 4 B per voxel
+    gat_bytes = (16.0 * S + 4.0 * n_vox * adj_launches_per_step) / adj_launches_per_step
+    kernels = {
+        "forward_f32": per_dtype["f32"],
+        "forward_bf16": per_dtype["bf16"],
+        "forward_f16": per_dtype["f16"],
+        "adjoint": {
+            "ms": adj_ms_step,
+            "ray_samples_per_s": S / (adj_ms_step * 1e-3),
+            "gather_ms_per_launch": gat_avg,
+            "table_ms_per_step": tab_ms / args.steps,
+            "launches_per_step": adj_launches_per_step,
+        },
+        "speedup_bf16_vs_f32": per_dtype["f32"]["ms"] / per_dtype["bf16"]["ms"],
+        "speedup_f16_vs_f32": per_dtype["f32"]["ms"] / per_dtype["f16"]["ms"],
+    }
+    # dominant kernel of the step
+    fwd_step_ms = fwd_ms / args.steps
+    if gat_ms >= fwd_ms / 3.0:
+        dom = "adjoint_gather"
+        achieved = gat_bytes / (gat_avg * 1e-3) / 1e9
+    else:
+        dom = "forward_f32"
+        achieved = per_dtype["f32"]["alg_GBps"]
+    roofline = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None,
+    }
+    out = {
+        "metric": "GJP ray-samples/s and % HBM roofline (fwd, adjoint, bf16) vs plain FP32 fwd",
+        "value": value,
+        "unit": "ray-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: {cfg.shape[0]}^3 random-ellipsoid volume, {cfg.n_views} "
+                        f"cone-beam views, {cfg.n_u}x{cfg.n_v} detector; step = FP32 forward + "
+                        f"adjoint + BF16 forward + FP16 forward",
+            "ray_samples_per_pass": S,
+            "rays_per_pass": n_rays,
+            "forward_ms_per_step": fwd_step_ms,
+        },
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        if vol_np is None:
+            vol_np = x.cpu().numpy()
+        log("timing the CPU oracle on a bounded ray sample")
+        out["cpu_baseline"] = cpu_baseline(cfg, vol_np, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -504,6 +504,20 @@ void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* pad
   a.vol = padded;
 }
 
+// 32-bit buffer addressing needs the padded volume below 4 GiB and the plane
+// stride within 24-bit multiplies; otherwise the kernels use 64-bit offsets.
+bool needs_idx64(const int* n, int dtype) {
+  const unsigned long long es = gjp::dtype_size(dtype);
+  const unsigned long long bytes = (unsigned long long)padded_elems(n) * es;
+  const unsigned long long s0 = (unsigned long long)(n[1] + 2) * (n[2] + 2) * es;
+  return bytes >= (1ull << 32) || s0 >= (1ull << 23);
+}
+
+void set_padded(FwdArgs& a, const void* padded, int dtype, const int* n) {
+  a.vol_base = padded;
+  a.vol_bytes = (unsigned long long)padded_elems(n) * gjp::dtype_size(dtype);
+}
+
 const void* padded_origin(const void* padded, int dtype, const FwdArgs& a) {
   const size_t es = gjp::dtype_size(dtype);
   return static_cast<const char*>(padded) + (size_t)(a.S0 + a.S1 + 1) * es;
@@ -533,9 +547,10 @@ gjp_status forward_with_tile(const gjp_geometry* g, const void* d_vol, int32_t d
   FwdArgs a;
   fill_fwd_args(g, d_views, nullptr, d_sino, tile, a);
   a.vol = padded_origin(padded, dtype, a);
+  set_padded(a, padded, dtype, g->n);
   st = gjp::launch_pad(d_vol, padded, dtype, g->n, s);
   if (st == GJP_OK)
-    st = gjp::launch_forward(a, dtype, g->weight, pe >= (1ll << 31), g->n_views, s);
+    st = gjp::launch_forward(a, dtype, g->weight, needs_idx64(g->n, dtype), g->n_views, s);
   const hipError_t fe = hipFreeAsync(padded, s);
   if (st != GJP_OK) return (gjp_status)st;
   if (fe != hipSuccess) return hip_fail(fe, "forward: free padded volume");
@@ -732,11 +747,12 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
     fill_fwd_args(g[i], d_views, nullptr, nullptr, t2, I.a);
     I.padded = static_cast<char*>(P->padded_all) + pad_off[i];
     I.a.vol = padded_origin(I.padded, dtypes[i], I.a);
+    set_padded(I.a, I.padded, dtypes[i], g[i]->n);
     I.n_views = g[i]->n_views;
     I.dtype = dtypes[i];
     I.weight = g[i]->weight;
     I.padded_elems = padded_elems(g[i]->n);
-    I.idx64 = I.padded_elems >= (1ll << 31) ? 1 : 0;
+    I.idx64 = needs_idx64(g[i]->n, dtypes[i]) ? 1 : 0;
     const int tile_rays = 256;
     const double per_item = (double)tile_rays * std::max(g[i]->n[0], std::max(g[i]->n[1], g[i]->n[2]));
     order.push_back({i, per_item});

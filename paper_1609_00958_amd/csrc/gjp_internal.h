@@ -56,6 +56,8 @@ struct FwdTile {
 // Arguments of one forward launch (one volume, a range of views).
 struct FwdArgs {
   const void* vol;      // padded volume, element (1,1,1) of the padded array
+  const void* vol_base; // padded volume, element (0,0,0)
+  unsigned long long vol_bytes;  // size of the padded volume in bytes
   float* sino;          // sinogram of the whole geometry
   const double* views;  // device, n_views x 12 grid units
   GridGeom G;

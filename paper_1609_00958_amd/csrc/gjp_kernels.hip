@@ -14,11 +14,11 @@
 // Adjoint: exact transpose of the forward. A table pass stores, per ray of a
 // chunk of views, the setup the forward computes (driving axis, sample range,
 // single-precision coefficients) and the sinogram value times the step length.
-// A gather pass assigns one lane per voxel (lanes along n2): for each view and
-// each driving axis present in it, the 2x2 in-plane neighbourhood of the voxel
-// is projected onto the detector, and every candidate ray in the resulting
-// pixel box recomputes the forward's weights with the same `sample_axis` code.
-// Each voxel is written once per chunk; no atomic accumulation.
+// A splat pass gives each workgroup a voxel tile in LDS; the rays of the view
+// chunk that can touch the tile recompute their samples on the tile's planes
+// with the same `sample_axis` code as the forward and add the weighted
+// contributions into LDS (waves own disjoint planes, so the sum order is
+// fixed). Each voxel is written to memory once per chunk; no global atomics.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -90,6 +90,82 @@ __global__ __launch_bounds__(256) void pad_kernel(const E* __restrict__ src, E* 
 // ---------------------------------------------------------------------------
 // Forward projection of one ray (Algorithm 1).
 // ---------------------------------------------------------------------------
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// Row pair (z, z+1) at byte offset `off` of the padded volume, widened to FP32.
+__device__ __forceinline__ void buf_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, const float*,
+                                         float& x0, float& x1) {
+  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  x0 = v.x;
+  x1 = v.y;
+}
+__device__ __forceinline__ void buf_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, const bf16_t*,
+                                         float& x0, float& x1) {
+  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  x0 = __uint_as_float(u << 16);
+  x1 = __uint_as_float(u & 0xffff0000u);
+}
+__device__ __forceinline__ void buf_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, const f16_t*,
+                                         float& x0, float& x1) {
+  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  x0 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
+  x1 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+}
+
+// Sampling loop for driving axes 0 and 1 on a padded volume below 4 GiB:
+// 32-bit byte offsets into a buffer resource, two samples per iteration so
+// that four row-pair loads are in flight per lane.
+template <typename T, int WF>
+__device__ __forceinline__ float fwd_loop_buf(const FwdArgs& a, const RaySetup& R) {
+  constexpr uint32_t es = sizeof(T);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.vol_base), (short)0, (int)(uint32_t)a.vol_bytes, 0x00020000);
+  const uint32_t Sm = (uint32_t)(R.m == 0 ? a.S0 : a.S1) * es;
+  const int Sa = (int)((R.m == 0 ? a.S1 : a.S0) * (long long)es);
+  const float h0 = a.G.hi[0], h1 = a.G.hi[1];
+  const float hia = (R.m == 0) ? h1 : h0;
+  const float hib = a.G.hi[2];
+  // padded frame: (plane + 1, row + 1, col + 1)
+  uint32_t off_m = (uint32_t)(R.i0 + 1) * Sm + (uint32_t)Sa + es;
+  float acc = 0.0f;
+  float fi = (float)R.i0;
+  int i = R.i0;
+  for (; i + 1 < R.i1; i += 2) {
+    int ia0, ib0, ia1, ib1;
+    float wfa0, wca0, wfb0, wcb0, wfa1, wca1, wfb1, wcb1;
+    sample_axis<WF>(fi, R.ga, R.ca, hia, ia0, wfa0, wca0);
+    sample_axis<WF>(fi, R.gb, R.cb, hib, ib0, wfb0, wcb0);
+    sample_axis<WF>(fi + 1.0f, R.ga, R.ca, hia, ia1, wfa1, wca1);
+    sample_axis<WF>(fi + 1.0f, R.gb, R.cb, hib, ib1, wfb1, wcb1);
+    const uint32_t o0 = (uint32_t)__mul24(ia0, Sa) + off_m + (uint32_t)ib0 * es;
+    const uint32_t o1 = (uint32_t)__mul24(ia1, Sa) + off_m + Sm + (uint32_t)ib1 * es;
+    float v00, v01, v10, v11, u00, u01, u10, u11;
+    buf_pair(rs, o0, (const T*)nullptr, v00, v01);
+    buf_pair(rs, o0 + (uint32_t)Sa, (const T*)nullptr, v10, v11);
+    buf_pair(rs, o1, (const T*)nullptr, u00, u01);
+    buf_pair(rs, o1 + (uint32_t)Sa, (const T*)nullptr, u10, u11);
+    acc = __builtin_fmaf(wfa0, __builtin_fmaf(wfb0, v00, wcb0 * v01), acc);
+    acc = __builtin_fmaf(wca0, __builtin_fmaf(wfb0, v10, wcb0 * v11), acc);
+    acc = __builtin_fmaf(wfa1, __builtin_fmaf(wfb1, u00, wcb1 * u01), acc);
+    acc = __builtin_fmaf(wca1, __builtin_fmaf(wfb1, u10, wcb1 * u11), acc);
+    fi += 2.0f;
+    off_m += 2 * Sm;
+  }
+  if (i < R.i1) {
+    int ia0, ib0;
+    float wfa0, wca0, wfb0, wcb0;
+    sample_axis<WF>(fi, R.ga, R.ca, hia, ia0, wfa0, wca0);
+    sample_axis<WF>(fi, R.gb, R.cb, hib, ib0, wfb0, wcb0);
+    const uint32_t o0 = (uint32_t)__mul24(ia0, Sa) + off_m + (uint32_t)ib0 * es;
+    float v00, v01, v10, v11;
+    buf_pair(rs, o0, (const T*)nullptr, v00, v01);
+    buf_pair(rs, o0 + (uint32_t)Sa, (const T*)nullptr, v10, v11);
+    acc = __builtin_fmaf(wfa0, __builtin_fmaf(wfb0, v00, wcb0 * v01), acc);
+    acc = __builtin_fmaf(wca0, __builtin_fmaf(wfb0, v10, wcb0 * v11), acc);
+  }
+  return acc;
+}
+
 template <typename T, int WF, bool IDX64>
 __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv) {
   using Index = std::conditional_t<IDX64, long long, int>;
@@ -99,25 +175,29 @@ __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int 
   float acc = 0.0f;
   float fi = (float)R.i0;
   if (R.m != 2) {
-    // transverse axes: ta (rows, strided) and 2 (contiguous pairs)
-    const Index Sm = (Index)(R.m == 0 ? a.S0 : a.S1);
-    const Index Sa = (Index)(R.m == 0 ? a.S1 : a.S0);
-    const float hia = (R.m == 0) ? a.G.hi[1] : a.G.hi[0];
-    const float hib = a.G.hi[2];
-    Index off_m = (Index)R.i0 * Sm;
-    for (int i = R.i0; i < R.i1; ++i) {
-      int ia, ib;
-      float wfa, wca, wfb, wcb;
-      sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
-      sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
-      const Index off = off_m + (Index)ia * Sa + (Index)ib;
-      float v00, v01, v10, v11;
-      load_pair(base + off, v00, v01);
-      load_pair(base + off + Sa, v10, v11);
-      acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
-      acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
-      fi += 1.0f;
-      off_m += Sm;
+    if constexpr (!IDX64) {
+      acc = fwd_loop_buf<T, WF>(a, R);
+    } else {
+      // transverse axes: ta (rows, strided) and 2 (contiguous pairs)
+      const Index Sm = (Index)(R.m == 0 ? a.S0 : a.S1);
+      const Index Sa = (Index)(R.m == 0 ? a.S1 : a.S0);
+      const float hia = (R.m == 0) ? a.G.hi[1] : a.G.hi[0];
+      const float hib = a.G.hi[2];
+      Index off_m = (Index)R.i0 * Sm;
+      for (int i = R.i0; i < R.i1; ++i) {
+        int ia, ib;
+        float wfa, wca, wfb, wcb;
+        sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
+        sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
+        const Index off = off_m + (Index)ia * Sa + (Index)ib;
+        float v00, v01, v10, v11;
+        load_pair(base + off, v00, v01);
+        load_pair(base + off + Sa, v10, v11);
+        acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
+        acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
+        fi += 1.0f;
+        off_m += Sm;
+      }
     }
   } else {
     // driving axis 2: both transverse axes strided, four single loads
@@ -208,77 +288,137 @@ __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint pass 2: voxel-driven gather over the chunk's views.
+// Adjoint pass 2: tile splat. A workgroup owns an ATX x ATY x ATZ voxel tile
+// held in LDS. For every view of the chunk and every driving axis present in
+// it, the rays whose footprint can touch the tile (the detector box of the
+// tile grown by one voxel) are staged in LDS in batches of 256, and their
+// samples on the tile's planes are recomputed with the forward's arithmetic;
+// the weighted contributions that land on tile voxels are added into LDS.
+//
+// Lane mapping: wave w owns planes [w T/4, (w+1) T/4) of the tile along the
+// driving axis (so waves never add to the same word and the summation order
+// is fixed), and within a wave lane = (plane, ray): the lanes of one LDS add
+// instruction cover PW consecutive planes of 64/PW rays taken far apart in the
+// batch, so they address distinct words. Odd plane strides in the padded LDS
+// layout spread consecutive planes over the banks. Each voxel is written to
+// memory once per chunk (no global atomics).
 // proj: per view 12 floats, rows (u, v, w) of the map from a grid point q to
-// homogeneous detector coordinates: u = (A_u . q + b_u) / (A_w . q + b_w).
+// homogeneous detector coordinates, u = (A_u . q + b_u) / (A_w . q + b_w).
 // ---------------------------------------------------------------------------
+constexpr int ATX = 32, ATY = 32, ATZ = 8;
+constexpr int ASY = ATZ + 1;            // y stride (odd)
+constexpr int ASX = ATY * ASY + 1;      // x stride (odd)
+constexpr int ATILE = ATX * ASX;        // LDS words of the tile
+constexpr int ABATCH = 256;             // rays staged per batch (one per thread)
+
+struct StagedRay {
+  float4 e0;  // {m | i0 << 2 | i1 << 17, ca, ga, cb}
+  float4 e1;  // {gb, y * scale, -, -}
+};
+
 template <int WF>
-__global__ __launch_bounds__(256) void adj_gather_kernel(
+__global__ __launch_bounds__(256) void adj_splat_kernel(
     const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
     const float4* __restrict__ table, const int* __restrict__ mask, int view0, int n_chunk,
     int accumulate, float* __restrict__ vol) {
-  const int z = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int x = blockIdx.z;
-  if (z >= G.n[2] || y >= G.n[1]) return;
-  const float fV[3] = {(float)x, (float)y, (float)z};
+  __shared__ float tile[ATILE];
+  __shared__ StagedRay stage[ABATCH];
+  const int x0 = blockIdx.z * ATX, y0 = blockIdx.y * ATY, z0 = blockIdx.x * ATZ;
+  for (int i = threadIdx.x; i < ATILE; i += 256) tile[i] = 0.0f;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const size_t per_view = (size_t)n_u * n_v;
-  const float e = 1.002f;     // widened neighbourhood (voxels)
-  const float margin = 0.05f; // widened pixel box (pixels)
-  float acc = 0.0f;
   for (int c = 0; c < n_chunk; ++c) {
     const int mk = mask[c];
     if (!mk) continue;
     const float* P = proj + 12 * (size_t)(view0 + c);
+    // detector box of the tile grown by one voxel (convex hull of 8 corners)
+    float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
+    bool full = false;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float cx = (q & 1) ? (float)(x0 + ATX) + 0.01f : (float)x0 - 1.01f;
+      const float cy = (q & 2) ? (float)(y0 + ATY) + 0.01f : (float)y0 - 1.01f;
+      const float cz = (q & 4) ? (float)(z0 + ATZ) + 0.01f : (float)z0 - 1.01f;
+      const float cu = __builtin_fmaf(P[0], cx, __builtin_fmaf(P[1], cy, __builtin_fmaf(P[2], cz, P[3])));
+      const float cv = __builtin_fmaf(P[4], cx, __builtin_fmaf(P[5], cy, __builtin_fmaf(P[6], cz, P[7])));
+      const float cw = __builtin_fmaf(P[8], cx, __builtin_fmaf(P[9], cy, __builtin_fmaf(P[10], cz, P[11])));
+      if (!(cw > 1.0e-6f)) full = true;
+      const float inv = 1.0f / cw;
+      const float uu = cu * inv, vv = cv * inv;
+      umin = fminf(umin, uu);
+      umax = fmaxf(umax, uu);
+      vmin = fminf(vmin, vv);
+      vmax = fmaxf(vmax, vv);
+    }
+    int iu_lo, iu_hi, iv_lo, iv_hi;
+    if (full) {
+      iu_lo = 0; iu_hi = n_u - 1; iv_lo = 0; iv_hi = n_v - 1;
+    } else {
+      const float margin = 0.05f;
+      iu_lo = max(0, (int)ceilf(fmaxf(umin - margin, -1.0f)));
+      iu_hi = min(n_u - 1, (int)floorf(fminf(umax + margin, (float)n_u)));
+      iv_lo = max(0, (int)ceilf(fmaxf(vmin - margin, -1.0f)));
+      iv_hi = min(n_v - 1, (int)floorf(fminf(vmax + margin, (float)n_v)));
+    }
+    const int nbv = iv_hi - iv_lo + 1;
+    const int nbox = (iu_hi >= iu_lo && nbv > 0) ? (iu_hi - iu_lo + 1) * nbv : 0;
+    if (nbox == 0) continue;
     const float4* T = table + 2 * per_view * (size_t)c;
-    const float pu = __builtin_fmaf(P[0], fV[0], __builtin_fmaf(P[1], fV[1], __builtin_fmaf(P[2], fV[2], P[3])));
-    const float pv = __builtin_fmaf(P[4], fV[0], __builtin_fmaf(P[5], fV[1], __builtin_fmaf(P[6], fV[2], P[7])));
-    const float pw = __builtin_fmaf(P[8], fV[0], __builtin_fmaf(P[9], fV[1], __builtin_fmaf(P[10], fV[2], P[11])));
     for (int m = 0; m < 3; ++m) {
       if (!(mk & (1 << m))) continue;
-      const int ta = (m == 0) ? 1 : 0;
-      const int tb = (m == 2) ? 1 : 2;
-      const int plane = (m == 0) ? x : ((m == 1) ? y : z);
-      const int Va = (ta == 0) ? x : y;
-      const int Vb = (tb == 1) ? y : z;
-      const float hia = (ta == 0) ? G.hi[0] : G.hi[1];
-      const float hib = (tb == 1) ? G.hi[1] : G.hi[2];
-      // candidate pixel box: image of the in-plane square V +- e (axes ta, tb)
-      const float ua = P[ta], va = P[4 + ta], wa = P[8 + ta];
-      const float ub = P[tb], vb = P[4 + tb], wb = P[8 + tb];
-      float umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
-      bool full = false;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float sa = (q & 1) ? e : -e;
-        const float sb = (q & 2) ? e : -e;
-        const float cu = __builtin_fmaf(sa, ua, __builtin_fmaf(sb, ub, pu));
-        const float cvv = __builtin_fmaf(sa, va, __builtin_fmaf(sb, vb, pv));
-        const float cw = __builtin_fmaf(sa, wa, __builtin_fmaf(sb, wb, pw));
-        if (!(cw > 1.0e-6f)) full = true;
-        const float inv = 1.0f / cw;
-        const float uu = cu * inv, vv = cvv * inv;
-        umin = fminf(umin, uu);
-        umax = fmaxf(umax, uu);
-        vmin = fminf(vmin, vv);
-        vmax = fmaxf(vmax, vv);
+      const int t0m = (m == 0) ? x0 : ((m == 1) ? y0 : z0);
+      const int Tm = (m == 0) ? ATX : ((m == 1) ? ATY : ATZ);
+      const int ta0 = (m == 0) ? y0 : x0;
+      const int Ta = (m == 0) ? ATY : ATX;
+      const int tb0 = (m == 2) ? y0 : z0;
+      const int Tb = (m == 2) ? ATY : ATZ;
+      const int Sm = (m == 0) ? ASX : ((m == 1) ? ASY : 1);
+      const int Sa = (m == 0) ? ASY : ASX;
+      const int Sb = (m == 2) ? ASY : 1;
+      const float hia = (m == 0) ? G.hi[1] : G.hi[0];
+      const float hib = (m == 2) ? G.hi[1] : G.hi[2];
+      const int pw_log2 = (Tm == 32) ? 3 : 1;  // planes per wave: Tm / 4 (8 or 2)
+      const int j = lane & ((1 << pw_log2) - 1);
+      const int q = lane >> pw_log2;
+      const int rq = 64 >> pw_log2;          // rays per instruction
+      const int lplane = (wave << pw_log2) + j;  // plane within the tile
+      const int plane = t0m + lplane;
+      const float fpl = (float)plane;
+      const int pidx = lplane * Sm;
+      // register prefetch of the first batch
+      float4 r0 = make_float4(__uint_as_float(3u), 0.0f, 0.0f, 0.0f);
+      float4 r1 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      {
+        const int r = threadIdx.x;
+        if (r < nbox) {
+          const int bu = r / nbv;
+          const float4* e = T + 2 * ((size_t)(iu_lo + bu) * n_v + (iv_lo + r - bu * nbv));
+          r0 = e[0];
+          r1 = e[1];
+        }
       }
-      int iu_lo, iu_hi, iv_lo, iv_hi;
-      if (full) {
-        iu_lo = 0; iu_hi = n_u - 1; iv_lo = 0; iv_hi = n_v - 1;
-      } else {
-        const float ulo = fmaxf(umin - margin, -1.0f), uhi = fminf(umax + margin, (float)n_u);
-        const float vlo = fmaxf(vmin - margin, -1.0f), vhi = fminf(vmax + margin, (float)n_v);
-        iu_lo = max(0, (int)ceilf(ulo));
-        iu_hi = min(n_u - 1, (int)floorf(uhi));
-        iv_lo = max(0, (int)ceilf(vlo));
-        iv_hi = min(n_v - 1, (int)floorf(vhi));
-      }
-      const float fplane = (float)plane;
-      for (int iu = iu_lo; iu <= iu_hi; ++iu) {
-        const float4* row = T + 2 * ((size_t)iu * n_v);
-        for (int iv = iv_lo; iv <= iv_hi; ++iv) {
-          const float4 e0 = row[2 * iv];
+      for (int base = 0; base < nbox; base += ABATCH) {
+        __syncthreads();  // previous batch consumed (and tile zeroed on entry)
+        stage[threadIdx.x].e0 = r0;
+        stage[threadIdx.x].e1 = r1;
+        __syncthreads();
+        {
+          const int r = base + ABATCH + (int)threadIdx.x;
+          r0 = make_float4(__uint_as_float(3u), 0.0f, 0.0f, 0.0f);
+          if (r < nbox) {
+            const int bu = r / nbv;
+            const float4* e = T + 2 * ((size_t)(iu_lo + bu) * n_v + (iv_lo + r - bu * nbv));
+            r0 = e[0];
+            r1 = e[1];
+          }
+        }
+        const int cnt = min(ABATCH, nbox - base);
+        const int K = (cnt + rq - 1) / rq;
+        for (int t = 0; t < K; ++t) {
+          const int k = q * K + t;  // rays of one instruction lie K apart in the batch
+          if (k >= cnt) continue;
+          const float4 e0 = stage[k].e0;
           const uint32_t mr = __float_as_uint(e0.x);
           const int em = (int)(mr & 3u);
           const int i0 = (int)((mr >> 2) & 0x7fffu);
@@ -286,20 +426,42 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(
           if (em != m || plane < i0 || plane >= i1) continue;
           int ia;
           float wfa, wca;
-          sample_axis<WF>(fplane, e0.z, e0.y, hia, ia, wfa, wca);
-          const float wA = (ia == Va) ? wfa : ((ia + 1 == Va) ? wca : 0.0f);
-          const float4 e1 = row[2 * iv + 1];
+          sample_axis<WF>(fpl, e0.z, e0.y, hia, ia, wfa, wca);
+          const int la = ia - ta0;
+          if (la < -1 || la >= Ta) continue;
+          const float4 e1 = stage[k].e1;
           int ib;
           float wfb, wcb;
-          sample_axis<WF>(fplane, e1.x, e0.w, hib, ib, wfb, wcb);
-          const float wB = (ib == Vb) ? wfb : ((ib + 1 == Vb) ? wcb : 0.0f);
-          acc = __builtin_fmaf(e1.y, wA * wB, acc);
+          sample_axis<WF>(fpl, e1.x, e0.w, hib, ib, wfb, wcb);
+          const int lb = ib - tb0;
+          if (lb < -1 || lb >= Tb) continue;
+          const int idx = pidx + la * Sa + lb * Sb;
+          const float w0 = e1.y * wfa, w1 = e1.y * wca;
+          if (la >= 0) {
+            if (lb >= 0) atomicAdd(&tile[idx], w0 * wfb);
+            if (lb + 1 < Tb) atomicAdd(&tile[idx + Sb], w0 * wcb);
+          }
+          if (la + 1 < Ta) {
+            if (lb >= 0) atomicAdd(&tile[idx + Sa], w1 * wfb);
+            if (lb + 1 < Tb) atomicAdd(&tile[idx + Sa + Sb], w1 * wcb);
+          }
         }
       }
+      __syncthreads();  // axis m done before another axis touches the tile
     }
   }
-  float* out = vol + ((size_t)x * G.n[1] + y) * G.n[2] + z;
-  *out = accumulate ? (*out + acc) : acc;
+  __syncthreads();
+  for (int i = threadIdx.x; i < ATX * ATY * ATZ; i += 256) {
+    const int lz = i % ATZ;
+    const int ly = (i / ATZ) % ATY;
+    const int lx = i / (ATZ * ATY);
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    if (x < G.n[0] && y < G.n[1] && z < G.n[2]) {
+      float* out = vol + ((size_t)x * G.n[1] + y) * G.n[2] + z;
+      const float v = tile[lx * ASX + ly * ASY + lz];
+      *out = accumulate ? (*out + v) : v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -443,16 +605,17 @@ int launch_adjoint_table(const gjp_geometry* g, const double* views, const float
 int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
                           const int* mask, int view0, int n_chunk, bool accumulate, float* vol,
                           hipStream_t s) {
-  dim3 grid((unsigned)((g->n[2] + 63) / 64), (unsigned)((g->n[1] + 3) / 4), (unsigned)g->n[0]);
+  dim3 grid((unsigned)((g->n[2] + ATZ - 1) / ATZ), (unsigned)((g->n[1] + ATY - 1) / ATY),
+            (unsigned)((g->n[0] + ATX - 1) / ATX));
   TimedLaunch t = timing_begin("adjoint_gather", s);
   if (g->weight == W_SPLINE)
-    adj_gather_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
-                                                     view0, n_chunk, accumulate ? 1 : 0, vol);
+    adj_splat_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
+                                                    view0, n_chunk, accumulate ? 1 : 0, vol);
   else
-    adj_gather_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
-                                                     view0, n_chunk, accumulate ? 1 : 0, vol);
+    adj_splat_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
+                                                    view0, n_chunk, accumulate ? 1 : 0, vol);
   timing_end("adjoint_gather", t, s);
-  return check_launch("adjoint gather kernel");
+  return check_launch("adjoint splat kernel");
 }
 
 int launch_batched_pad(const BatchInst* d_insts, int n_inst, hipStream_t s) {

@@ -1,0 +1,205 @@
+"""GPU tests of the batched persistent launch, the autograd wrapper and the
+full-size workload configurations (checked on sampled rays)."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import cuda, note, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gjp():
+    import paper_1609_00958_amd as m
+    return m
+
+
+def _oracle_geom(oracle_mod, G):
+    beam = oracle_mod.CONE if G.beam == 0 else oracle_mod.PARALLEL
+    return oracle_mod.Geometry(G.shape, G.views, G.n_u, G.n_v, beam=beam,
+                               voxel_size=G.voxel_size, center=G.center, weight=G.weight)
+
+
+# ---------------------------------------------------------------------------
+# batched persistent launch
+# ---------------------------------------------------------------------------
+def _small_instances(gjp, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(7):
+        shape = tuple(int(s) for s in rng.integers(9, 60, size=3))
+        n_views = int(rng.integers(3, 12))
+        n_u, n_v = (int(s) for s in rng.integers(5, 90, size=2))
+        beam = "cone" if k % 2 == 0 else "parallel"
+        gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+        G = gjp.Geometry(shape, gen(seed + k, n_views, shape, n_u, n_v), n_u, n_v, beam=beam,
+                         weight="spline" if k == 3 else "linear")
+        out.append(G)
+    return out
+
+
+def test_batched_equals_single_launches(gjp):
+    import torch
+    dev = cuda()
+    geoms = _small_instances(gjp, 200)
+    dtypes = [torch.float32, torch.bfloat16, torch.float32, torch.float16, torch.float32,
+              torch.float32, torch.bfloat16]
+    for rep in range(3):   # first call captures the graph, later calls replay it
+        gen = torch.Generator().manual_seed(300 + rep)
+        vols = [torch.rand(G.shape, generator=gen).to(dev).to(dt) for G, dt in zip(geoms, dtypes)]
+        note(f"batched rep {rep}")
+        outs = gjp.forward_batched(vols, geoms)
+        torch.cuda.synchronize()
+        for v, G, o in zip(vols, geoms, outs):
+            ref = gjp.forward(v, G)
+            assert torch.equal(o, ref)
+
+
+def test_batched_matches_oracle(gjp, oracle_mod):
+    import torch
+    dev = cuda()
+    geoms = _small_instances(gjp, 210)
+    gen = torch.Generator().manual_seed(311)
+    vols = [torch.rand(G.shape, generator=gen) for G in geoms]
+    note("batched vs oracle")
+    outs = gjp.forward_batched([v.to(dev) for v in vols], geoms)
+    for v, G, o in zip(vols, geoms, outs):
+        want = oracle_mod.forward(_oracle_geom(oracle_mod, G), v.numpy())
+        assert rel_l2(o.cpu().numpy(), want) <= 1e-5
+
+
+# ---------------------------------------------------------------------------
+# autograd wrapper: gradient = adjoint; central differences of the quadratic loss
+# ---------------------------------------------------------------------------
+def test_autograd_gradient_is_adjoint(gjp):
+    import torch
+    dev = cuda()
+    cfg = workloads.config("c1")
+    G = gjp.Geometry.from_config(cfg)
+    x = torch.rand(cfg.shape, generator=torch.Generator().manual_seed(7)).to(dev)
+    x.requires_grad_(True)
+    w = torch.randn(G.sino_shape, generator=torch.Generator().manual_seed(8)).to(dev)
+    note("autograd")
+    y = gjp.project(x, G)
+    (y * w).sum().backward()
+    assert torch.equal(x.grad, gjp.back(w, G))
+    # bf16 input: gradient comes back in the input's dtype
+    xb = x.detach().to(torch.bfloat16).requires_grad_(True)
+    (gjp.project(xb, G) * w).sum().backward()
+    assert xb.grad.dtype == torch.bfloat16
+
+
+def test_finite_differences_gpu(gjp):
+    """L(x) = 0.5 ||Ax - b||^2 is quadratic, so the central difference equals the
+    gradient A^T(Ax - b) up to rounding; losses accumulated in FP64."""
+    import torch
+    dev = cuda()
+    shape = (48, 48, 48)
+    G = gjp.Geometry(shape, workloads.random_cone_views(121, 16, shape, 72, 72), 72, 72)
+    gen = torch.Generator().manual_seed(122)
+    x = torch.rand(shape, generator=gen).to(dev)
+    b = (gjp.forward(x, G) + 0.5 * torch.randn(G.sino_shape, generator=gen).to(dev)).detach()
+    x0 = torch.rand(shape, generator=gen).to(dev)
+
+    def loss(z):
+        r = gjp.forward(z, G).double() - b.double()
+        return 0.5 * float((r * r).sum())
+
+    note("finite differences")
+    grad = gjp.back(gjp.forward(x0, G) - b, G).double()
+    rng = np.random.default_rng(123)
+    idx = [tuple(int(t) for t in rng.integers(8, 40, size=3)) for _ in range(64)]
+    # the loss is quadratic, so the central difference is exact for any step; a
+    # large step keeps the FP32 rounding of the affected rays (~1e-6 relative,
+    # divided by 2 eps) well under the tolerance
+    eps = float(x0.abs().max())
+    for v in idx:
+        xp = x0.clone()
+        xm = x0.clone()
+        xp[v] += eps
+        xm[v] -= eps
+        fd = (loss(xp) - loss(xm)) / (2 * eps)
+        g = float(grad[v])
+        assert abs(fd - g) <= 1e-4 * max(abs(g), 1e-3 * float(grad.abs().max())), (v, fd, g)
+
+
+def test_gradient_descent_monotone(gjp):
+    import torch
+    dev = cuda()
+    shape = (40, 40, 40)
+    G = gjp.Geometry(shape, gjp.views_circular_cone(48, 160.0, 240.0, 1.0, 1.0, 60, 60), 60, 60)
+    ells = workloads.random_ellipsoids(131, shape)
+    truth = torch.from_numpy(workloads.rasterize(ells, shape)).to(dev)
+    b = gjp.forward(truth, G)
+    # step 1/L with L from power iterations on A^T A
+    v = torch.rand(shape, generator=torch.Generator().manual_seed(132)).to(dev)
+    for _ in range(10):
+        v = gjp.back(gjp.forward(v, G), G)
+        lam = float(v.norm())
+        v = v / lam
+    x = torch.zeros(shape, device=dev, requires_grad=True)
+    losses = []
+    note("gradient descent")
+    for _ in range(8):
+        x.grad = None
+        loss = 0.5 * ((gjp.project(x, G) - b) ** 2).sum()
+        loss.backward()
+        losses.append(float(loss))
+        with torch.no_grad():
+            x -= x.grad / (1.05 * lam)
+    assert all(b2 < b1 for b1, b2 in zip(losses, losses[1:]))
+    assert losses[-1] < 0.5 * losses[0]
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations in the benchmark's launch setup, on sampled rays
+# ---------------------------------------------------------------------------
+def _full_config_check(gjp, oracle_mod, name, n_rays, dtypes=("f32",)):
+    import torch
+    dev = cuda()
+    cfg = workloads.config(name)
+    note(f"{name}: rasterise {cfg.shape}")
+    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    G = gjp.Geometry.from_config(cfg)
+    og = oracle_mod.geometry_for(cfg)
+    rays = workloads.sample_rays(51, n_rays, cfg.n_views, cfg.n_u, cfg.n_v)
+    idx = torch.from_numpy(rays.astype(np.int64))
+    for dt in dtypes:
+        xd = {"f32": x, "bf16": x.to(torch.bfloat16), "f16": x.to(torch.float16)}[dt]
+        note(f"{name}: forward {dt}")
+        y = gjp.forward(xd, G)
+        got = y[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+        del y
+        host = xd.float().cpu().numpy()
+        want = oracle_mod.forward_rays(og, host, rays)
+        assert rel_l2(got, want) <= 1e-5, (name, dt)
+        if dt != "f32":
+            want32 = oracle_mod.forward_rays(og, x.cpu().numpy(), rays)
+            assert rel_l2(got, want32) <= 5e-3, (name, dt)
+        del host, xd
+    return cfg, G, og, x
+
+
+def test_full_c2_forward_and_adjoint(gjp, oracle_mod):
+    import torch
+    cfg, G, og, x = _full_config_check(gjp, oracle_mod, "c2", 4000)
+    dev = x.device
+    # adjoint: sinogram non-zero on three views only, so the oracle stays cheap
+    y = torch.zeros(G.sino_shape)
+    gen = torch.Generator().manual_seed(52)
+    for v in (0, 45, 181):
+        y[v] = torch.rand(G.n_u, G.n_v, generator=gen)
+    note("c2: adjoint")
+    got = gjp.back(y.to(dev), G).cpu().numpy()
+    want = oracle_mod.adjoint(og, y.numpy())
+    assert rel_l2(got, want) <= 1e-5
+
+
+def test_full_c3_forward(gjp, oracle_mod):
+    _full_config_check(gjp, oracle_mod, "c3", 3000)
+
+
+@pytest.mark.slow
+def test_full_c5a_forward_16bit(gjp, oracle_mod):
+    _full_config_check(gjp, oracle_mod, "c5a", 2000, dtypes=("bf16", "f16"))
