@@ -21,7 +21,7 @@
 #include <thread>
 #include <vector>
 
-#include "../../include/gjp.h"
+#include "gjp.h"
 #include "gjp_internal.h"
 
 using gjp::BatchInst;
@@ -269,6 +269,32 @@ static void detector_projection(const double* v, int beam, float* P) {
   for (int k = 0; k < 12; ++k) P[k] = (float)R[k];
 }
 
+// True when, in every view, dv has no component on axes 0 and 1 and no ray is
+// driven by axis 2 (|r_2| stays below max(|r_0|, |r_1|) with a safety
+// factor). Then d_0, d_1, r_0, r_1 and the source do not depend on iv, so the
+// ray setup of all rays of a detector column yields the same driving axis and
+// in-plane coefficients, bit for bit.
+static bool columns_share_inplane_setup(const gjp_geometry& g) {
+  for (int v = 0; v < g.n_views; ++v) {
+    const double* o = g.views_grid.data() + 12 * (size_t)v;
+    if (o[9] != 0.0 || o[10] != 0.0) return false;
+    if (g.beam == GJP_PARALLEL) {
+      if (!(fabs(o[2]) * (1.0 + 1e-9) < fmax(fabs(o[0]), fabs(o[1])))) return false;
+      continue;
+    }
+    for (int iu = 0; iu < g.n_u; ++iu) {
+      const double d0 = o[3] + (double)iu * o[6];
+      const double d1 = o[4] + (double)iu * o[7];
+      const double r0 = d0 - o[0], r1 = d1 - o[1];
+      const double M = fmax(fabs(r0), fabs(r1));
+      const double z0 = o[5] + (double)iu * o[8] - o[2];
+      const double z1 = o[5] + (double)iu * o[8] + (double)(g.n_v - 1) * o[11] - o[2];
+      if (!(fmax(fabs(z0), fabs(z1)) * (1.0 + 1e-9) < M)) return false;
+    }
+  }
+  return true;
+}
+
 extern "C" gjp_status gjp_create_geometry(const gjp_geometry_desc* d, gjp_geometry** out) {
   if (!d || !out) return fail(GJP_EINVAL, "gjp_create_geometry: null pointer");
   *out = nullptr;
@@ -339,6 +365,7 @@ extern "C" gjp_status gjp_create_geometry(const gjp_geometry_desc* d, gjp_geomet
     }
     detector_projection(o, d->beam, g->proj.data() + 12 * v);
   }
+  g->separable = columns_share_inplane_setup(*g);
   *out = g.release();
   return GJP_OK;
 }
@@ -626,29 +653,36 @@ extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sin
   int st = gjp::geometry_device(g, &d_views, &d_proj);
   if (st != GJP_OK) return (gjp_status)st;
   const size_t per_view = (size_t)g->n_u * g->n_v;
-  const size_t entry = 2 * sizeof(float4);
+  const size_t entry = (g->separable ? 1 : 2) * sizeof(float4);
+  const size_t col_entry = g->separable ? sizeof(float4) : 0;
   const size_t budget = (size_t)512 << 20;
-  long long chunk = (long long)(budget / (per_view * entry));
+  long long chunk = (long long)(budget / (per_view * entry + (size_t)g->n_u * col_entry));
   if (chunk < 1) chunk = 1;
   if (chunk > g->n_views) chunk = g->n_views;
   void* table = nullptr;
   void* mask = nullptr;
+  void* cols = nullptr;
   GJP_HIP(scratch_alloc(&table, (size_t)chunk * per_view * entry, s), "back_project: table");
   hipError_t e = scratch_alloc(&mask, (size_t)chunk * sizeof(int), s);
+  if (e == hipSuccess && g->separable)
+    e = scratch_alloc(&cols, (size_t)chunk * g->n_u * col_entry, s);
   if (e != hipSuccess) {
     (void)hipFreeAsync(table, s);
-    return hip_fail(e, "back_project: mask");
+    if (mask) (void)hipFreeAsync(mask, s);
+    return hip_fail(e, "back_project: scratch");
   }
   for (int v0 = 0; v0 < g->n_views && st == GJP_OK; v0 += (int)chunk) {
     const int nc = (int)std::min<long long>(chunk, g->n_views - v0);
     st = gjp::launch_zero_ints(static_cast<int*>(mask), nc, s);
     if (st == GJP_OK)
       st = gjp::launch_adjoint_table(g, d_views, d_sino, v0, nc, static_cast<float4*>(table),
-                                     static_cast<int*>(mask), s);
+                                     static_cast<float4*>(cols), static_cast<int*>(mask), s);
     if (st == GJP_OK)
       st = gjp::launch_adjoint_gather(g, d_proj, static_cast<const float4*>(table),
+                                      static_cast<const float4*>(cols),
                                       static_cast<const int*>(mask), v0, nc, v0 > 0, d_vol, s);
   }
+  if (cols) (void)hipFreeAsync(cols, s);
   const hipError_t f1 = hipFreeAsync(table, s);
   const hipError_t f2 = hipFreeAsync(mask, s);
   if (st != GJP_OK) return (gjp_status)st;

@@ -23,6 +23,10 @@ struct gjp_geometry {
   std::vector<double> views_grid;   // n_views x 12, grid units
   std::vector<float> proj;          // n_views x 12: detector projection rows (u, v, w)
   gjp::GridGeom gg;
+  // Every view has dv without in-plane component and no ray driven by axis 2:
+  // the rays of a detector column share their in-plane coefficients, and the
+  // adjoint uses the column-form gather.
+  bool separable = false;
 
   // device copies, per device (created on first use)
   struct Dev {
@@ -77,10 +81,11 @@ int launch_zero_ints(int* p, int n, hipStream_t s);
 int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,
                    hipStream_t s);
 int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,
-                         int view0, int n_chunk, float4* table, int* mask, hipStream_t s);
+                         int view0, int n_chunk, float4* table, float4* cols, int* mask,
+                         hipStream_t s);
 int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
-                          const int* mask, int view0, int n_chunk, bool accumulate,
-                          float* vol, hipStream_t s);
+                          const float4* cols, const int* mask, int view0, int n_chunk,
+                          bool accumulate, float* vol, hipStream_t s);
 
 // Batched forward (gjp_batched.cpp / gjp_kernels.hip).
 struct BatchInst {

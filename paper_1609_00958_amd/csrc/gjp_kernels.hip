@@ -245,14 +245,18 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
 
 // ---------------------------------------------------------------------------
 // Adjoint pass 1: per-ray table for views [view0, view0 + n_chunk).
-// Entry (two float4): {m | i0 << 2 | i1 << 17, ca, ga, cb}, {gb, y * scale, 0, 0}.
+// General layout, two float4 per ray: {m | i0 << 2 | i1 << 17, ca, ga, cb},
+// {gb, y * scale, 0, 0}. Column layout (see adj_gather_sep_kernel): one float4
+// per ray {m | i0 << 2 | i1 << 17, cb, gb, y * scale} and one per detector
+// column {m, ca, ga, 0}.
 // mask[c] collects the driving axes that have samples in view view0 + c.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict__ views,
                                                         const GridGeom G,
                                                         const float* __restrict__ sino, int n_u,
                                                         int n_v, int view0, long long n_rays,
-                                                        float4* __restrict__ table,
+                                                        int separable, float4* __restrict__ table,
+                                                        float4* __restrict__ cols,
                                                         int* __restrict__ mask) {
   const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
   const long long per_view = (long long)n_u * n_v;
@@ -267,8 +271,14 @@ __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict
     ray_setup(views + 12 * (size_t)(view0 + cv), G, iu, iv, R);
     const float y = sino[(size_t)(view0 + cv) * per_view + rem];
     const uint32_t mr = (uint32_t)R.m | ((uint32_t)R.i0 << 2) | ((uint32_t)R.i1 << 17);
-    table[2 * r] = make_float4(__uint_as_float(mr), R.ca, R.ga, R.cb);
-    table[2 * r + 1] = make_float4(R.gb, y * R.scale, 0.0f, 0.0f);
+    if (separable) {
+      table[r] = make_float4(__uint_as_float(mr), R.cb, R.gb, y * R.scale);
+      if (iv == 0)
+        cols[(size_t)cv * n_u + iu] = make_float4(__uint_as_float((uint32_t)R.m), R.ca, R.ga, 0.0f);
+    } else {
+      table[2 * r] = make_float4(__uint_as_float(mr), R.ca, R.ga, R.cb);
+      table[2 * r + 1] = make_float4(R.gb, y * R.scale, 0.0f, 0.0f);
+    }
     if (R.i1 > R.i0) bits = 1 << R.m;
   }
   // one atomicOr per (wavefront, view) with samples
@@ -414,9 +424,11 @@ __global__ __launch_bounds__(256) void adj_splat_kernel(
           }
         }
         const int cnt = min(ABATCH, nbox - base);
-        const int K = (cnt + rq - 1) / rq;
+        // rays of one instruction lie K apart in the batch (distinct voxels);
+        // an odd K puts their 32-byte stage entries in distinct LDS banks
+        const int K = ((cnt + rq - 1) / rq) | 1;
         for (int t = 0; t < K; ++t) {
-          const int k = q * K + t;  // rays of one instruction lie K apart in the batch
+          const int k = q * K + t;
           if (k >= cnt) continue;
           const float4 e0 = stage[k].e0;
           const uint32_t mr = __float_as_uint(e0.x);
@@ -429,7 +441,7 @@ __global__ __launch_bounds__(256) void adj_splat_kernel(
           sample_axis<WF>(fpl, e0.z, e0.y, hia, ia, wfa, wca);
           const int la = ia - ta0;
           if (la < -1 || la >= Ta) continue;
-          const float4 e1 = stage[k].e1;
+          const float2 e1 = *reinterpret_cast<const float2*>(&stage[k].e1);
           int ib;
           float wfb, wcb;
           sample_axis<WF>(fpl, e1.x, e0.w, hib, ib, wfb, wcb);
@@ -461,6 +473,123 @@ __global__ __launch_bounds__(256) void adj_splat_kernel(
       const float v = tile[lx * ASX + ly * ASY + lz];
       *out = accumulate ? (*out + v) : v;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint pass 2, column form. When dv has no in-plane component and no ray is
+// driven by axis 2, all rays of a detector column share the driving axis m and
+// the coefficients (c_a, g_a) of the in-plane transverse coordinate: the ray
+// setup computes them from bitwise identical inputs. A lane owns one voxel
+// (lanes along axis 2). For each view and driving axis, the candidate columns
+// are those whose in-plane coordinate on the voxel's plane can lie within one
+// voxel (wave-uniform), and in each column the candidate rays are the few whose
+// axis-2 coordinate can lie within one voxel of the lane's (an affine range in
+// the ray index, since the detector's axis-2 direction keeps the projective
+// denominator independent of z). Every weight is recomputed with the forward's
+// sample_axis; a voxel sums its contributions in registers and is written
+// once per chunk. No LDS, no barriers, no atomics.
+// ---------------------------------------------------------------------------
+template <int WF>
+__global__ __launch_bounds__(256) void adj_gather_sep_kernel(
+    const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
+    const float4* __restrict__ rays, const float4* __restrict__ cols,
+    const int* __restrict__ mask, int view0, int n_chunk, int accumulate,
+    float* __restrict__ vol) {
+  const int z = blockIdx.x * 64 + (int)(threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int x = blockIdx.z;
+  if (y >= G.n[1]) return;
+  const bool zin = z < G.n[2];
+  const float fx = (float)x, fy = (float)y, fz = (float)z;
+  const float hx = G.hi[0], hy = G.hi[1], hz = G.hi[2];
+  const float e = 1.002f;       // widened neighbourhood (voxels)
+  const float margin = 0.05f;   // widened ranges (pixels)
+  float acc = 0.0f;
+  for (int c = 0; c < n_chunk; ++c) {
+    const int mk = mask[c];
+    if (!mk) continue;
+    const float* P = proj + 12 * (size_t)(view0 + c);
+    const float4* C = cols + (size_t)c * n_u;
+    const float4* RY = rays + (size_t)c * n_u * n_v;
+    for (int m = 0; m < 2; ++m) {
+      if (!(mk & (1 << m))) continue;
+      const int plane = (m == 0) ? x : y;
+      const float fplane = (m == 0) ? fx : fy;
+      const int va = (m == 0) ? y : x;
+      const float ha = (m == 0) ? hy : hx;
+      // candidate columns: u of (plane, va -+ e); u does not depend on z here
+      const float qx0 = (m == 0) ? fx : fx - e, qy0 = (m == 0) ? fy - e : fy;
+      const float qx1 = (m == 0) ? fx : fx + e, qy1 = (m == 0) ? fy + e : fy;
+      const float un0 = __builtin_fmaf(P[0], qx0, __builtin_fmaf(P[1], qy0, P[3]));
+      const float w0 = __builtin_fmaf(P[8], qx0, __builtin_fmaf(P[9], qy0, P[11]));
+      const float un1 = __builtin_fmaf(P[0], qx1, __builtin_fmaf(P[1], qy1, P[3]));
+      const float w1 = __builtin_fmaf(P[8], qx1, __builtin_fmaf(P[9], qy1, P[11]));
+      int iu_lo = 0, iu_hi = n_u - 1;
+      if (w0 > 1.0e-6f && w1 > 1.0e-6f) {
+        const float u0 = un0 / w0, u1 = un1 / w1;
+        iu_lo = max(0, (int)ceilf(fmaxf(fminf(u0, u1) - margin, -1.0f)));
+        iu_hi = min(n_u - 1, (int)floorf(fminf(fmaxf(u0, u1) + margin, (float)n_u)));
+      }
+      for (int iu = iu_lo; iu <= iu_hi; ++iu) {
+        const float4 col = C[iu];
+        if ((int)__float_as_uint(col.x) != m) continue;
+        int ia;
+        float wfa, wca;
+        sample_axis<WF>(fplane, col.z, col.y, ha, ia, wfa, wca);
+        const float wA = (ia == va) ? wfa : ((ia + 1 == va) ? wca : 0.0f);
+        if (wA == 0.0f) continue;
+        // v of the column's rays on this plane: (A + B z) / W
+        const float pa = __builtin_fmaf(fplane, col.z, col.y);
+        const float qx = (m == 0) ? fx : pa, qy = (m == 0) ? pa : fy;
+        const float A = __builtin_fmaf(P[4], qx, __builtin_fmaf(P[5], qy, P[7]));
+        const float W = __builtin_fmaf(P[8], qx, __builtin_fmaf(P[9], qy, P[11]));
+        int iv_lo = 0, iv_hi = n_v - 1;
+        if (W > 1.0e-6f) {
+          const float inv = 1.0f / W;
+          const float v0 = (A + P[6] * (fz - e)) * inv;
+          const float v1 = (A + P[6] * (fz + e)) * inv;
+          iv_lo = max(0, (int)ceilf(fmaxf(fminf(v0, v1) - margin, -1.0f)));
+          iv_hi = min(n_v - 1, (int)floorf(fminf(fmaxf(v0, v1) + margin, (float)n_v)));
+        }
+        if (!zin) iv_hi = iv_lo - 1;
+        const float4* R = RY + (size_t)iu * n_v;
+        // the first four candidates are loaded together (indices clamped into
+        // the column), then consumed; wider ranges fall through to a loop
+        float4 rr[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rr[k] = R[min(iv_lo + k, n_v - 1)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float4 r = rr[k];
+          const uint32_t mr = __float_as_uint(r.x);
+          const int i0 = (int)((mr >> 2) & 0x7fffu);
+          const int i1 = (int)(mr >> 17);
+          int ib;
+          float wfb, wcb;
+          sample_axis<WF>(fplane, r.z, r.y, hz, ib, wfb, wcb);
+          float wB = (ib == z) ? wfb : ((ib + 1 == z) ? wcb : 0.0f);
+          if (iv_lo + k > iv_hi || plane < i0 || plane >= i1) wB = 0.0f;
+          acc = __builtin_fmaf(r.w, wA * wB, acc);
+        }
+        for (int iv = iv_lo + 4; iv <= iv_hi; ++iv) {
+          const float4 r = R[iv];
+          const uint32_t mr = __float_as_uint(r.x);
+          const int i0 = (int)((mr >> 2) & 0x7fffu);
+          const int i1 = (int)(mr >> 17);
+          if (plane < i0 || plane >= i1) continue;
+          int ib;
+          float wfb, wcb;
+          sample_axis<WF>(fplane, r.z, r.y, hz, ib, wfb, wcb);
+          const float wB = (ib == z) ? wfb : ((ib + 1 == z) ? wcb : 0.0f);
+          acc = __builtin_fmaf(r.w, wA * wB, acc);
+        }
+      }
+    }
+  }
+  if (zin) {
+    float* out = vol + ((size_t)x * G.n[1] + y) * G.n[2] + z;
+    *out = accumulate ? (*out + acc) : acc;
   }
 }
 
@@ -591,31 +720,43 @@ int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_vi
 }
 
 int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,
-                         int view0, int n_chunk, float4* table, int* mask, hipStream_t s) {
+                         int view0, int n_chunk, float4* table, float4* cols, int* mask,
+                         hipStream_t s) {
   const long long n_rays = (long long)n_chunk * g->n_u * g->n_v;
   const long long nb = (n_rays + 255) / 256;
   if (nb > 0xffffffffll) return set_error(-4, "adjoint: view chunk too large");
   TimedLaunch t = timing_begin("adjoint_table", s);
   adj_table_kernel<<<(unsigned)nb, 256, 0, s>>>(views, g->gg, sino, g->n_u, g->n_v, view0,
-                                                 n_rays, table, mask);
+                                                 n_rays, g->separable ? 1 : 0, table, cols, mask);
   timing_end("adjoint_table", t, s);
   return check_launch("adjoint table kernel");
 }
 
 int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
-                          const int* mask, int view0, int n_chunk, bool accumulate, float* vol,
-                          hipStream_t s) {
-  dim3 grid((unsigned)((g->n[2] + ATZ - 1) / ATZ), (unsigned)((g->n[1] + ATY - 1) / ATY),
-            (unsigned)((g->n[0] + ATX - 1) / ATX));
+                          const float4* cols, const int* mask, int view0, int n_chunk,
+                          bool accumulate, float* vol, hipStream_t s) {
   TimedLaunch t = timing_begin("adjoint_gather", s);
-  if (g->weight == W_SPLINE)
-    adj_splat_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
-                                                    view0, n_chunk, accumulate ? 1 : 0, vol);
-  else
-    adj_splat_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
-                                                    view0, n_chunk, accumulate ? 1 : 0, vol);
+  const int acc = accumulate ? 1 : 0;
+  if (g->separable) {
+    dim3 grid((unsigned)((g->n[2] + 63) / 64), (unsigned)((g->n[1] + 3) / 4), (unsigned)g->n[0]);
+    if (g->weight == W_SPLINE)
+      adj_gather_sep_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table,
+                                                           cols, mask, view0, n_chunk, acc, vol);
+    else
+      adj_gather_sep_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table,
+                                                           cols, mask, view0, n_chunk, acc, vol);
+  } else {
+    dim3 grid((unsigned)((g->n[2] + ATZ - 1) / ATZ), (unsigned)((g->n[1] + ATY - 1) / ATY),
+              (unsigned)((g->n[0] + ATX - 1) / ATX));
+    if (g->weight == W_SPLINE)
+      adj_splat_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
+                                                      view0, n_chunk, acc, vol);
+    else
+      adj_splat_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, mask,
+                                                      view0, n_chunk, acc, vol);
+  }
   timing_end("adjoint_gather", t, s);
-  return check_launch("adjoint splat kernel");
+  return check_launch("adjoint kernel");
 }
 
 int launch_batched_pad(const BatchInst* d_insts, int n_inst, hipStream_t s) {
