@@ -641,6 +641,9 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
 // ---------------------------------------------------------------------------
 // adjoint
 // ---------------------------------------------------------------------------
+// Views per launch of the column-form gather (see gjp_back_project).
+static const int kGatherViews = 16;
+
 extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sino, float* d_vol,
                                        void* stream) {
   if (!g) return fail(GJP_EINVAL, "back_project: geometry is null");
@@ -677,10 +680,17 @@ extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sin
     if (st == GJP_OK)
       st = gjp::launch_adjoint_table(g, d_views, d_sino, v0, nc, static_cast<float4*>(table),
                                      static_cast<float4*>(cols), static_cast<int*>(mask), s);
-    if (st == GJP_OK)
+    // The gather runs over sub-chunks of views so that all resident
+    // workgroups read the same few views' tables (L2-sized working set);
+    // each sub-chunk reads and writes the volume once.
+    const int sub = g->separable ? kGatherViews : nc;
+    for (int c0 = 0; c0 < nc && st == GJP_OK; c0 += sub) {
+      const int ns = std::min(sub, nc - c0);
       st = gjp::launch_adjoint_gather(g, d_proj, static_cast<const float4*>(table),
                                       static_cast<const float4*>(cols),
-                                      static_cast<const int*>(mask), v0, nc, v0 > 0, d_vol, s);
+                                      static_cast<const int*>(mask), v0, c0, ns,
+                                      v0 + c0 > 0, d_vol, s);
+    }
   }
   if (cols) (void)hipFreeAsync(cols, s);
   const hipError_t f1 = hipFreeAsync(table, s);

@@ -84,7 +84,7 @@ int launch_adjoint_table(const gjp_geometry* g, const double* views, const float
                          int view0, int n_chunk, float4* table, float4* cols, int* mask,
                          hipStream_t s);
 int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
-                          const float4* cols, const int* mask, int view0, int n_chunk,
+                          const float4* cols, const int* mask, int view0, int c0, int n_chunk,
                           bool accumulate, float* vol, hipStream_t s);
 
 // Batched forward (gjp_batched.cpp / gjp_kernels.hip).

@@ -480,33 +480,36 @@ __global__ __launch_bounds__(256) void adj_splat_kernel(
 // Adjoint pass 2, column form. When dv has no in-plane component and no ray is
 // driven by axis 2, all rays of a detector column share the driving axis m and
 // the coefficients (c_a, g_a) of the in-plane transverse coordinate: the ray
-// setup computes them from bitwise identical inputs. A lane owns one voxel
-// (lanes along axis 2). For each view and driving axis, the candidate columns
-// are those whose in-plane coordinate on the voxel's plane can lie within one
-// voxel (wave-uniform), and in each column the candidate rays are the few whose
-// axis-2 coordinate can lie within one voxel of the lane's (an affine range in
-// the ray index, since the detector's axis-2 direction keeps the projective
-// denominator independent of z). Every weight is recomputed with the forward's
-// sample_axis; a voxel sums its contributions in registers and is written
-// once per chunk. No LDS, no barriers, no atomics.
+// setup computes them from bitwise identical inputs. A lane owns two voxels
+// adjacent along axis 2 (lanes along axis 2). For each view and driving axis,
+// the candidate columns are those whose in-plane coordinate on the voxels'
+// plane can lie within one voxel (wave-uniform); in each column the candidate
+// rays are the few whose axis-2 coordinate can reach the pair, an affine range
+// in the ray index (the detector's axis-2 direction keeps the projective
+// denominator independent of z). Each candidate sample is evaluated once, with
+// the forward's sample_axis, for both voxels; each voxel sums its
+// contributions in registers and is written once per launch. No LDS, no
+// barriers, no atomics.
 // ---------------------------------------------------------------------------
 template <int WF>
 __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
     const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
     const float4* __restrict__ rays, const float4* __restrict__ cols,
-    const int* __restrict__ mask, int view0, int n_chunk, int accumulate,
+    const int* __restrict__ mask, int view0, int c0, int n_chunk, int accumulate,
     float* __restrict__ vol) {
-  const int z = blockIdx.x * 64 + (int)(threadIdx.x & 63);
+  // a lane owns the voxel pair (x, y, z) and (x, y, z + 1)
+  const int z = 2 * (blockIdx.x * 64 + (int)(threadIdx.x & 63));
   const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int x = blockIdx.z;
   if (y >= G.n[1]) return;
   const bool zin = z < G.n[2];
   const float fx = (float)x, fy = (float)y, fz = (float)z;
   const float hx = G.hi[0], hy = G.hi[1], hz = G.hi[2];
-  const float e = 1.002f;       // widened neighbourhood (voxels)
+  const float e = 0.002f;       // widened neighbourhood (voxels)
   const float margin = 0.05f;   // widened ranges (pixels)
-  float acc = 0.0f;
-  for (int c = 0; c < n_chunk; ++c) {
+  constexpr int NC = 6;         // candidate rays loaded together per column
+  float acc0 = 0.0f, acc1 = 0.0f;
+  for (int c = c0; c < c0 + n_chunk; ++c) {
     const int mk = mask[c];
     if (!mk) continue;
     const float* P = proj + 12 * (size_t)(view0 + c);
@@ -518,9 +521,10 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
       const float fplane = (m == 0) ? fx : fy;
       const int va = (m == 0) ? y : x;
       const float ha = (m == 0) ? hy : hx;
-      // candidate columns: u of (plane, va -+ e); u does not depend on z here
-      const float qx0 = (m == 0) ? fx : fx - e, qy0 = (m == 0) ? fy - e : fy;
-      const float qx1 = (m == 0) ? fx : fx + e, qy1 = (m == 0) ? fy + e : fy;
+      // candidate columns: u of (plane, va -+ (1 + e)); u does not depend on z here
+      const float ea = 1.0f + e;
+      const float qx0 = (m == 0) ? fx : fx - ea, qy0 = (m == 0) ? fy - ea : fy;
+      const float qx1 = (m == 0) ? fx : fx + ea, qy1 = (m == 0) ? fy + ea : fy;
       const float un0 = __builtin_fmaf(P[0], qx0, __builtin_fmaf(P[1], qy0, P[3]));
       const float w0 = __builtin_fmaf(P[8], qx0, __builtin_fmaf(P[9], qy0, P[11]));
       const float un1 = __builtin_fmaf(P[0], qx1, __builtin_fmaf(P[1], qy1, P[3]));
@@ -546,21 +550,22 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
         const float W = __builtin_fmaf(P[8], qx, __builtin_fmaf(P[9], qy, P[11]));
         int iv_lo = 0, iv_hi = n_v - 1;
         if (W > 1.0e-6f) {
+          // rays whose axis-2 coordinate lies in [z - 1, z + 2) reach the pair
           const float inv = 1.0f / W;
-          const float v0 = (A + P[6] * (fz - e)) * inv;
-          const float v1 = (A + P[6] * (fz + e)) * inv;
+          const float v0 = (A + P[6] * (fz - 1.0f - e)) * inv;
+          const float v1 = (A + P[6] * (fz + 2.0f + e)) * inv;
           iv_lo = max(0, (int)ceilf(fmaxf(fminf(v0, v1) - margin, -1.0f)));
           iv_hi = min(n_v - 1, (int)floorf(fminf(fmaxf(v0, v1) + margin, (float)n_v)));
         }
         if (!zin) iv_hi = iv_lo - 1;
         const float4* R = RY + (size_t)iu * n_v;
-        // the first four candidates are loaded together (indices clamped into
+        // the first NC candidates are loaded together (indices clamped into
         // the column), then consumed; wider ranges fall through to a loop
-        float4 rr[4];
+        float4 rr[NC];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) rr[k] = R[min(iv_lo + k, n_v - 1)];
+        for (int k = 0; k < NC; ++k) rr[k] = R[min(iv_lo + k, n_v - 1)];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NC; ++k) {
           const float4 r = rr[k];
           const uint32_t mr = __float_as_uint(r.x);
           const int i0 = (int)((mr >> 2) & 0x7fffu);
@@ -568,11 +573,15 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
           int ib;
           float wfb, wcb;
           sample_axis<WF>(fplane, r.z, r.y, hz, ib, wfb, wcb);
-          float wB = (ib == z) ? wfb : ((ib + 1 == z) ? wcb : 0.0f);
-          if (iv_lo + k > iv_hi || plane < i0 || plane >= i1) wB = 0.0f;
-          acc = __builtin_fmaf(r.w, wA * wB, acc);
+          const int d = ib - z;  // the sample's floor relative to the pair
+          float b0 = (d == 0) ? wfb : ((d == -1) ? wcb : 0.0f);
+          float b1 = (d == 1) ? wfb : ((d == 0) ? wcb : 0.0f);
+          const bool ok = (iv_lo + k <= iv_hi) && plane >= i0 && plane < i1;
+          const float wa = ok ? r.w * wA : 0.0f;
+          acc0 = __builtin_fmaf(wa, b0, acc0);
+          acc1 = __builtin_fmaf(wa, b1, acc1);
         }
-        for (int iv = iv_lo + 4; iv <= iv_hi; ++iv) {
+        for (int iv = iv_lo + NC; iv <= iv_hi; ++iv) {
           const float4 r = R[iv];
           const uint32_t mr = __float_as_uint(r.x);
           const int i0 = (int)((mr >> 2) & 0x7fffu);
@@ -581,15 +590,20 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
           int ib;
           float wfb, wcb;
           sample_axis<WF>(fplane, r.z, r.y, hz, ib, wfb, wcb);
-          const float wB = (ib == z) ? wfb : ((ib + 1 == z) ? wcb : 0.0f);
-          acc = __builtin_fmaf(r.w, wA * wB, acc);
+          const int d = ib - z;
+          const float b0 = (d == 0) ? wfb : ((d == -1) ? wcb : 0.0f);
+          const float b1 = (d == 1) ? wfb : ((d == 0) ? wcb : 0.0f);
+          const float wa = r.w * wA;
+          acc0 = __builtin_fmaf(wa, b0, acc0);
+          acc1 = __builtin_fmaf(wa, b1, acc1);
         }
       }
     }
   }
   if (zin) {
     float* out = vol + ((size_t)x * G.n[1] + y) * G.n[2] + z;
-    *out = accumulate ? (*out + acc) : acc;
+    out[0] = accumulate ? (out[0] + acc0) : acc0;
+    if (z + 1 < G.n[2]) out[1] = accumulate ? (out[1] + acc1) : acc1;
   }
 }
 
@@ -733,19 +747,23 @@ int launch_adjoint_table(const gjp_geometry* g, const double* views, const float
 }
 
 int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
-                          const float4* cols, const int* mask, int view0, int n_chunk,
+                          const float4* cols, const int* mask, int view0, int c0, int n_chunk,
                           bool accumulate, float* vol, hipStream_t s) {
   TimedLaunch t = timing_begin("adjoint_gather", s);
   const int acc = accumulate ? 1 : 0;
   if (g->separable) {
-    dim3 grid((unsigned)((g->n[2] + 63) / 64), (unsigned)((g->n[1] + 3) / 4), (unsigned)g->n[0]);
+    dim3 grid((unsigned)((g->n[2] + 127) / 128), (unsigned)((g->n[1] + 3) / 4),
+              (unsigned)g->n[0]);
     if (g->weight == W_SPLINE)
       adj_gather_sep_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table,
-                                                           cols, mask, view0, n_chunk, acc, vol);
+                                                           cols, mask, view0, c0, n_chunk, acc,
+                                                           vol);
     else
       adj_gather_sep_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table,
-                                                           cols, mask, view0, n_chunk, acc, vol);
+                                                           cols, mask, view0, c0, n_chunk, acc,
+                                                           vol);
   } else {
+    if (c0 != 0) return set_error(-4, "adjoint: the tile splat takes whole chunks");
     dim3 grid((unsigned)((g->n[2] + ATZ - 1) / ATZ), (unsigned)((g->n[1] + ATY - 1) / ATY),
               (unsigned)((g->n[0] + ATX - 1) / ATX));
     if (g->weight == W_SPLINE)
