@@ -43,6 +43,25 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch (fetch + write) of `kernel` from the committed rocprofv3
+    summary of this workload, or None if there is none or the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_1609_00958_amd import profiling
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("source_sha256") != profiling.source_hash():
+        return None
+    k = data.get("kernels", {}).get(kernel, {})
+    fb, wb = k.get("fetch_bytes_per_launch"), k.get("write_bytes_per_launch")
+    if fb is None or wb is None:
+        return None
+    return fb + wb
+
+
 def cpu_baseline(cfg, vol_np, target_s: float):
     """Time the FP64 oracle forward on a bounded random sample of the workload's rays."""
     import oracle
@@ -85,7 +104,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--autotune", action="store_true", help="autotune the forward tile first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy before the steps (untimed), a "
@@ -213,7 +232,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": measured_traffic(args.workload, "adjoint_gather" if dom == "adjoint_gather"
+                                    else "forward_f32"),
     }
     out = {
         "metric": "GJP ray-samples/s and % HBM roofline (fwd, adjoint, bf16) vs plain FP32 fwd",

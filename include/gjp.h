@@ -94,12 +94,14 @@ gjp_status gjp_forward_project(const gjp_geometry *g, const void *d_vol, int32_t
 
 /* Adjoint (exact transpose) x = A^T y of gjp_forward_project for the same
    geometry: every sample's single-precision weights are recomputed exactly as
-   the forward computes them, and each voxel gathers its contributions from
-   the candidate rays of every view (voxel-driven, no atomic accumulation;
-   the result is bitwise reproducible). d_sino: device, n_views*n_u*n_v
-   floats. d_vol: device, n0*n1*n2 floats, overwritten. Per-ray tables for a
-   chunk of views are taken from the stream-ordered pool during the call.
-   Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
+   the forward computes them. When every view's dv is parallel to axis 2 and no
+   ray is driven by axis 2 (circular trajectories), each voxel gathers its
+   contributions in registers; otherwise voxel tiles accumulate in LDS with
+   waves owning disjoint planes. No global atomics; each voxel is written by
+   one thread per launch, and the summation order is fixed. d_sino: device,
+   n_views*n_u*n_v floats. d_vol: device, n0*n1*n2 floats, overwritten.
+   Per-ray tables for a chunk of views are taken from the stream-ordered pool
+   during the call. Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
 gjp_status gjp_back_project(const gjp_geometry *g, const float *d_sino, float *d_vol,
                             void *stream);
 
@@ -143,6 +145,12 @@ gjp_status gjp_count_samples(const gjp_geometry *g, uint64_t *out);
    Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
 gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
                                 float *d_sino, void *stream, int32_t *tile_v_out);
+
+/* Fix the ray-tile shape that forward and batched calls use for geometries
+   of this shape signature and dtype, as gjp_autotune_forward would (tile_v =
+   detector pixels along v per wavefront row: 64, 32 or 16). Every tile shape
+   gives bitwise identical sinograms. Host-only. Errors: GJP_EINVAL. */
+gjp_status gjp_set_forward_tile(const gjp_geometry *g, int32_t vol_dtype, int32_t tile_v);
 
 /* Per-kernel GPU timing for benchmarks. While enabled, each launch of the
    library's main kernels is bracketed by HIP events on its stream.

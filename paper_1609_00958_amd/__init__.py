@@ -8,13 +8,15 @@ HIP kernels behind the C ABI declared in include/gjp.h.
 from ._lib import (BF16, CONE, F16, F32, PARALLEL, W_LINEAR, W_SPLINE, GJPError,  # noqa: F401
                    lib)
 from .projector import (Geometry, autotune, back, forward, forward_batched,  # noqa: F401
-                        project, timing_enable, timing_read, timing_reset, views_circular_cone,
+                        project, set_forward_tile, timing_enable, timing_read, timing_reset,
+                        views_circular_cone,
                         views_parallel)
 
 lib()  # load the HIP library now: there is no fallback path
 
 __all__ = [
     "Geometry", "forward", "back", "forward_batched", "project", "autotune",
-    "views_circular_cone", "views_parallel", "timing_enable", "timing_read", "timing_reset",
+    "views_circular_cone", "views_parallel", "set_forward_tile", "timing_enable", "timing_read",
+    "timing_reset",
     "GJPError",
 ]

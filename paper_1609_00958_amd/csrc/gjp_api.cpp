@@ -638,6 +638,21 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
   return GJP_OK;
 }
 
+extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dtype,
+                                           int32_t tile_v) {
+  if (!g) return fail(GJP_EINVAL, "gjp_set_forward_tile: geometry is null");
+  if (vol_dtype != GJP_F32 && vol_dtype != GJP_BF16 && vol_dtype != GJP_F16)
+    return fail(GJP_EINVAL, "gjp_set_forward_tile: unknown dtype");
+  FwdTile t;
+  if (tile_v == 64) t.tile_v_log2 = 6;
+  else if (tile_v == 32) t.tile_v_log2 = 5;
+  else if (tile_v == 16) t.tile_v_log2 = 4;
+  else return fail(GJP_EINVAL, "gjp_set_forward_tile: tile_v must be 64, 32 or 16");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[tune_key(g, vol_dtype)] = t;
+  return GJP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // adjoint
 // ---------------------------------------------------------------------------

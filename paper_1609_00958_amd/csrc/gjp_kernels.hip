@@ -166,6 +166,87 @@ __device__ __forceinline__ float fwd_loop_buf(const FwdArgs& a, const RaySetup& 
   return acc;
 }
 
+// Row pair at (scalar byte offset + lane byte offset), for the row-uniform loop.
+__device__ __forceinline__ void buf_pair_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                           const float*, float& x0, float& x1) {
+  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  x0 = v.x;
+  x1 = v.y;
+}
+__device__ __forceinline__ void buf_pair_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                           const bf16_t*, float& x0, float& x1) {
+  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  x0 = __uint_as_float(u << 16);
+  x1 = __uint_as_float(u & 0xffff0000u);
+}
+__device__ __forceinline__ void buf_pair_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                           const f16_t*, float& x0, float& x1) {
+  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  x0 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
+  x1 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Sampling loop for a wavefront whose rays all share the driving axis (0 or
+// 1) and the in-plane coefficients (ca, ga): the row coordinate, its weights
+// and the row offset of every plane are the same for all lanes. Lane l
+// evaluates them for plane base + l of each block of 64 planes, and the loop
+// broadcasts plane j's values with readlane; lanes only evaluate the axis-2
+// coordinate. Each lane accumulates exactly the terms, in the same order and
+// with the same arithmetic, as fwd_loop_buf, so the results are identical.
+template <typename T, int WF>
+__device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const RaySetup& R, int lo,
+                                                     int hi) {
+  constexpr uint32_t es = sizeof(T);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void*>(a.vol_base), (short)0, (int)(uint32_t)a.vol_bytes, 0x00020000);
+  const int m = __builtin_amdgcn_readfirstlane(R.m);
+  const uint32_t Sm = (uint32_t)(m == 0 ? a.S0 : a.S1) * es;
+  const uint32_t Sa = (uint32_t)((m == 0 ? a.S1 : a.S0) * (long long)es);
+  const float hia = (m == 0) ? a.G.hi[1] : a.G.hi[0];
+  const float hib = a.G.hi[2];
+  const float ca = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, R.ca)));
+  const float ga = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, R.ga)));
+  const int lane = (int)(threadIdx.x & 63);
+  float acc = 0.0f;
+  for (int base = lo; base < hi; base += 64) {
+    int ia_l;
+    float wfa_l, wca_l;
+    sample_axis<WF>((float)(base + lane), ga, ca, hia, ia_l, wfa_l, wca_l);
+    // byte offset of (plane + 1, row + 1, 0) in the padded volume
+    const uint32_t row_l = (uint32_t)(base + lane + 1) * Sm + (uint32_t)(ia_l + 1) * Sa;
+    const int cnt = min(64, hi - base);
+    for (int j = 0; j < cnt; ++j) {
+      const int i = base + j;
+      const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)row_l, j);
+      const float wfa = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wfa_l), j));
+      const float wca = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wca_l), j));
+      if (i >= R.i0 && i < R.i1) {
+        int ib;
+        float wfb, wcb;
+        sample_axis<WF>((float)i, R.gb, R.cb, hib, ib, wfb, wcb);
+        const uint32_t vo = (uint32_t)(ib + 1) * es;
+        float v00, v01, v10, v11;
+        buf_pair_s(rs, vo, row, (const T*)nullptr, v00, v01);
+        buf_pair_s(rs, vo, row + Sa, (const T*)nullptr, v10, v11);
+        acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
+        acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
+      }
+    }
+  }
+  return acc;
+}
+
 template <typename T, int WF, bool IDX64>
 __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv) {
   using Index = std::conditional_t<IDX64, long long, int>;
@@ -176,7 +257,23 @@ __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int 
   float fi = (float)R.i0;
   if (R.m != 2) {
     if constexpr (!IDX64) {
-      acc = fwd_loop_buf<T, WF>(a, R);
+      // row-uniform wavefront: every lane with samples shares m, ca and ga
+      const bool has = R.i1 > R.i0;
+      const uint64_t hv = __ballot(has);
+      bool uniform = false;
+      if (hv != 0) {
+        const int leader = __ffsll((unsigned long long)hv) - 1;
+        const int lm = __shfl(R.m, leader);
+        const float lca = __shfl(R.ca, leader), lga = __shfl(R.ga, leader);
+        uniform = __ballot(has && (R.m != lm || R.ca != lca || R.ga != lga)) == 0;
+      }
+      if (uniform && __builtin_amdgcn_readfirstlane(R.m) != 2) {
+        const int lo = __builtin_amdgcn_readfirstlane(wave_min(has ? R.i0 : 0x7fffffff));
+        const int hi = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i1 : -1));
+        acc = fwd_loop_rowuniform<T, WF>(a, R, lo, hi);
+      } else {
+        acc = fwd_loop_buf<T, WF>(a, R);
+      }
     } else {
       // transverse axes: ta (rows, strided) and 2 (contiguous pairs)
       const Index Sm = (Index)(R.m == 0 ? a.S0 : a.S1);
@@ -281,20 +378,17 @@ __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict
     }
     if (R.i1 > R.i0) bits = 1 << R.m;
   }
-  // one atomicOr per (wavefront, view) with samples
-  uint64_t pending = __ballot(bits != 0);
-  while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int lcv = __shfl(cv, leader);
-    const bool same = (bits != 0) && (cv == lcv);
-    const uint64_t grp = __ballot(same);
-    int orbits = 0;
-    if (__ballot(same && (bits & 1))) orbits |= 1;
-    if (__ballot(same && (bits & 2))) orbits |= 2;
-    if (__ballot(same && (bits & 4))) orbits |= 4;
-    if ((int)(threadIdx.x & 63) == leader) atomicOr(&mask[lcv], orbits);
-    pending &= ~grp;
-  }
+  // driving axes per view: OR within the workgroup (LDS), then one global OR
+  // per (workgroup, view); integer OR is order independent
+  __shared__ int s_bits[256];
+  s_bits[threadIdx.x] = 0;
+  __syncthreads();
+  const long long r0 = (long long)blockIdx.x * 256;
+  const int cv0 = (int)(r0 / per_view);
+  if (bits) atomicOr(&s_bits[cv - cv0], bits);
+  __syncthreads();
+  const int b = s_bits[threadIdx.x];
+  if (b) atomicOr(&mask[cv0 + (int)threadIdx.x], b);
 }
 
 // ---------------------------------------------------------------------------

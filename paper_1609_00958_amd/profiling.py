@@ -1,0 +1,149 @@
+"""Summaries of rocprofv3 output for the projector's kernels.
+
+    python -m paper_1609_00958_amd.profiling --trace DIR [--fetch DIR --write DIR]
+        --label NAME --command "..." --out-md FILE [--out-json FILE]
+
+`--trace` is the output directory of `rocprofv3 --kernel-trace --stats
+--output-format csv`; `--fetch` / `--write` are those of two `rocprofv3 --pmc
+FETCH_SIZE` and `--pmc WRITE_SIZE` runs. Hardware byte counters are scaled by
+what the same counter reads for a plain device-to-device copy of 1 GiB found in
+the same run (the benchmark's `--calibrate-copy` option issues one), and
+reported per launch. The JSON output records a hash of the kernel sources so
+that a reader can tell whether the counters still describe the current code.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/gjp_kernels.hip", "csrc/gjp_ray.h")
+
+SHORT = (
+    ("fwd_kernel<float", "forward_f32"),
+    ("fwd_kernel<gjp::bf16_t", "forward_bf16"),
+    ("fwd_kernel<gjp::f16_t", "forward_f16"),
+    ("adj_gather_sep_kernel", "adjoint_gather"),
+    ("adj_splat_kernel", "adjoint_gather"),
+    ("adj_table_kernel", "adjoint_table"),
+    ("pad_kernel", "pad"),
+    ("batched_fwd_kernel", "batched"),
+    ("batched_pad_kernel", "batched_pad"),
+    ("__amd_rocclr_copyBuffer", "copy"),
+)
+
+
+def short_name(name: str):
+    for key, short in SHORT:
+        if key in name:
+            return short
+    return None
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _one(dirpath: str, suffix: str) -> str:
+    hits = glob.glob(os.path.join(dirpath, "**", "*" + suffix), recursive=True)
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+    return sorted(hits)[0]
+
+
+def kernel_stats(trace_dir: str):
+    out = {}
+    with open(_one(trace_dir, "kernel_stats.csv")) as f:
+        for row in csv.DictReader(f):
+            s = short_name(row["Name"])
+            if s is None:
+                continue
+            calls = int(row["Calls"])
+            total = float(row["TotalDurationNs"])
+            cur = out.setdefault(s, {"calls": 0, "total_ns": 0.0})
+            cur["calls"] += calls
+            cur["total_ns"] += total
+    for v in out.values():
+        v["avg_ms"] = v["total_ns"] / max(v["calls"], 1) / 1e6
+    return out
+
+
+def counter_per_dispatch(pmc_dir: str):
+    """{dispatch id: (kernel name, summed counter value)} of one --pmc run."""
+    vals = collections.OrderedDict()
+    with open(_one(pmc_dir, "counter_collection.csv")) as f:
+        for row in csv.DictReader(f):
+            d = int(row["Dispatch_Id"])
+            name, v = vals.get(d, (row["Kernel_Name"], 0.0))
+            vals[d] = (name, v + float(row["Counter_Value"]))
+    return vals
+
+
+def scaled_traffic(pmc_dir: str, ref_bytes: float = float(1 << 30)):
+    """Average scaled bytes per dispatch per kernel, and the copy scale factor."""
+    vals = counter_per_dispatch(pmc_dir)
+    ref = [v for (n, v) in vals.values() if short_name(n) == "copy"]
+    if not ref:
+        raise RuntimeError("no reference copy dispatch in " + pmc_dir)
+    ref_kib = max(ref)
+    scale = (ref_bytes / 1024.0) / ref_kib
+    acc = collections.defaultdict(list)
+    for n, v in vals.values():
+        s = short_name(n)
+        if s and s != "copy":
+            acc[s].append(v * 1024.0 * scale)
+    return {k: sum(v) / len(v) for k, v in acc.items()}, scale
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--label", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--out-md", required=True)
+    ap.add_argument("--out-json")
+    a = ap.parse_args()
+    stats = kernel_stats(a.trace)
+    fetch = write = None
+    fscale = wscale = None
+    if a.fetch and a.write:
+        fetch, fscale = scaled_traffic(a.fetch)
+        write, wscale = scaled_traffic(a.write)
+    lines = [f"# {a.label}", "", "Command(s):", "", "```", a.command, "```", "",
+             "| kernel | launches | avg ms / launch | HBM fetch GB / launch | HBM write GB / launch |",
+             "|---|---|---|---|---|"]
+    for k in sorted(stats, key=lambda k: -stats[k]["total_ns"]):
+        f = f"{fetch[k] / 1e9:.3f}" if fetch and k in fetch else "-"
+        w = f"{write[k] / 1e9:.3f}" if write and k in write else "-"
+        lines.append(f"| {k} | {stats[k]['calls']} | {stats[k]['avg_ms']:.3f} | {f} | {w} |")
+    if fscale:
+        lines += ["", f"Byte counters scaled by the 1 GiB copy reference: FETCH_SIZE x {fscale:.3f}, "
+                      f"WRITE_SIZE x {wscale:.3f}."]
+    lines += ["", f"Kernel source sha256: `{source_hash()}`", ""]
+    with open(a.out_md, "w") as f:
+        f.write("\n".join(lines))
+    if a.out_json:
+        data = {"label": a.label, "command": a.command, "source_sha256": source_hash(),
+                "kernels": {k: {"launches": v["calls"], "avg_ms": v["avg_ms"],
+                                "fetch_bytes_per_launch": fetch.get(k) if fetch else None,
+                                "write_bytes_per_launch": write.get(k) if write else None}
+                            for k, v in stats.items()},
+                "copy_scale": {"fetch": fscale, "write": wscale}}
+        with open(a.out_json, "w") as f:
+            json.dump(data, f, indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

@@ -216,6 +216,14 @@ def autotune(vol, geom: Geometry, out=None) -> int:
     return int(tv.value)
 
 
+def set_forward_tile(geom: Geometry, dtype, tile_v: int) -> None:
+    """Fix the forward tile shape (tile_v = 64, 32 or 16) for this geometry's
+    shape signature and a torch dtype."""
+    torch = _torch()
+    code = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}[dtype]
+    check(lib().gjp_set_forward_tile(geom.handle, code, int(tile_v)))
+
+
 def timing_enable(on: bool = True) -> None:
     check(lib().gjp_timing_enable(1 if on else 0))
 

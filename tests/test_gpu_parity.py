@@ -157,6 +157,12 @@ def test_deterministic(gjp):
     assert torch.equal(a, b)
     c, d = gjp.back(a, G), gjp.back(a, G)
     assert torch.equal(c, d)
+    # random orientations: the tile-splat adjoint
+    shape = (30, 34, 40)
+    G = gjp.Geometry(shape, workloads.random_cone_views(6, 5, shape, 50, 60), 50, 60)
+    y = torch.rand(G.sino_shape, generator=torch.Generator().manual_seed(7)).to(dev)
+    c, d = gjp.back(y, G), gjp.back(y, G)
+    assert torch.equal(c, d)
 
 
 # ---------------------------------------------------------------------------
@@ -208,3 +214,63 @@ def test_tile_shapes_bitwise_identical(gjp):
     tv = gjp.autotune(x, G)
     assert tv in (64, 32, 16)
     assert torch.equal(gjp.forward(x, G), ref)
+
+
+# ---------------------------------------------------------------------------
+# 64-bit addressing: a padded plane beyond 24-bit multiplies (or a padded
+# volume beyond 4 GiB) selects the 64-bit offset path; small non-cubic grids
+# with large planes reach it cheaply.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,shape", [("f32", (5, 1500, 1500)), ("bf16", (4, 2100, 2100))])
+def test_forward_64bit_offsets(gjp, oracle_mod, dtype, shape):
+    import torch
+    dev = cuda()
+    # plane stride in bytes of the padded copy exceeds 2^23
+    es = 4 if dtype == "f32" else 2
+    assert (shape[1] + 2) * (shape[2] + 2) * es >= (1 << 23)
+    n_views, n_u, n_v = 6, 40, 90
+    for beam in ("cone", "parallel"):
+        gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+        G = gjp.Geometry(shape, gen(101, n_views, shape, n_u, n_v), n_u, n_v, beam=beam)
+        og = _oracle_geom(oracle_mod, G)
+        vol = np.random.default_rng(102).uniform(0, 1, size=shape).astype(np.float32)
+        x = _to_dev(vol, dev)
+        if dtype == "bf16":
+            x = x.to(torch.bfloat16)
+            vol = x.float().cpu().numpy()
+        note(f"64-bit offsets {dtype} {shape} {beam}")
+        y = gjp.forward(x, G).cpu().numpy()
+        rays = workloads.sample_rays(103, 1500, n_views, n_u, n_v)
+        got = y[rays[:, 0], rays[:, 1], rays[:, 2]]
+        want = oracle_mod.forward_rays(og, vol, rays)
+        assert rel_l2(got, want) <= TOL32
+
+
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+def test_circular_tiles_bitwise_and_adjoint(gjp, oracle_mod, beam):
+    """Circular trajectories: the 64-wide tile takes the row-uniform sampling
+    loop, the 32- and 16-wide tiles the per-lane loop; all give identical
+    sinograms. The adjoint takes the column-form gather."""
+    import torch
+    dev = cuda()
+    shape = (40, 44, 70)
+    n_views, n_u, n_v = 12, 70, 100
+    if beam == "cone":
+        G = gjp.Geometry.circular_cone(shape, n_views, n_u, n_v, 180.0, 300.0, 1.0, 1.2)
+    else:
+        G = gjp.Geometry.parallel(shape, n_views, n_u, n_v, 0.9, 0.8)
+    og = _oracle_geom(oracle_mod, G)
+    vol = workloads.rasterize(workloads.random_ellipsoids(111, shape), shape)
+    x = _to_dev(vol, dev)
+    outs = []
+    for dt in (torch.float32, torch.bfloat16):
+        for tv in (64, 32, 16):
+            gjp.set_forward_tile(G, dt, tv)
+            note(f"circular {beam} tile {tv} {dt}")
+            outs.append(gjp.forward(x.to(dt), G))
+        assert torch.equal(outs[-3], outs[-2]) and torch.equal(outs[-3], outs[-1])
+    assert rel_l2(outs[0].cpu().numpy(), oracle_mod.forward(og, vol)) <= TOL32
+    y = np.random.default_rng(112).uniform(0, 1, size=G.sino_shape).astype(np.float32)
+    note(f"circular {beam} adjoint")
+    got = gjp.back(_to_dev(y, dev), G).cpu().numpy()
+    assert rel_l2(got, oracle_mod.adjoint(og, y)) <= TOL32

@@ -203,3 +203,10 @@ def test_full_c3_forward(gjp, oracle_mod):
 @pytest.mark.slow
 def test_full_c5a_forward_16bit(gjp, oracle_mod):
     _full_config_check(gjp, oracle_mod, "c5a", 2000, dtypes=("bf16", "f16"))
+
+
+@pytest.mark.slow
+def test_full_c5b_forward_2048(gjp, oracle_mod):
+    """2048^3 FP32 (34 GB, 64-bit offsets), 64 views, 3072^2 detector, checked on
+    sampled rays against the oracle reading the same volume on the host."""
+    _full_config_check(gjp, oracle_mod, "c5b", 1500)
