@@ -204,19 +204,19 @@ __device__ __forceinline__ int wave_max(int v) {
 // broadcasts plane j's values with readlane; lanes only evaluate the axis-2
 // coordinate. Each lane accumulates exactly the terms, in the same order and
 // with the same arithmetic, as fwd_loop_buf, so the results are identical.
+//
+// m, ca and ga are the shared (wave-uniform) values; every one of the 64 lanes
+// must be active, since each computes the row data of one plane.
 template <typename T, int WF>
-__device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const RaySetup& R, int lo,
-                                                     int hi) {
+__device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const RaySetup& R, int m,
+                                                     float ca, float ga, int lo, int hi) {
   constexpr uint32_t es = sizeof(T);
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<void*>(a.vol_base), (short)0, (int)(uint32_t)a.vol_bytes, 0x00020000);
-  const int m = __builtin_amdgcn_readfirstlane(R.m);
   const uint32_t Sm = (uint32_t)(m == 0 ? a.S0 : a.S1) * es;
   const uint32_t Sa = (uint32_t)((m == 0 ? a.S1 : a.S0) * (long long)es);
   const float hia = (m == 0) ? a.G.hi[1] : a.G.hi[0];
   const float hib = a.G.hi[2];
-  const float ca = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, R.ca)));
-  const float ga = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, R.ga)));
   const int lane = (int)(threadIdx.x & 63);
   float acc = 0.0f;
   for (int base = lo; base < hi; base += 64) {
@@ -226,54 +226,87 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
     // byte offset of (plane + 1, row + 1, 0) in the padded volume
     const uint32_t row_l = (uint32_t)(base + lane + 1) * Sm + (uint32_t)(ia_l + 1) * Sa;
     const int cnt = min(64, hi - base);
-    for (int j = 0; j < cnt; ++j) {
+    // two planes per iteration: both planes' loads are issued before either
+    // is consumed; each plane still contributes in order and only inside the
+    // lane's own sample range
+    for (int j = 0; j < cnt; j += 2) {
       const int i = base + j;
-      const uint32_t row = (uint32_t)__builtin_amdgcn_readlane((int)row_l, j);
-      const float wfa = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wfa_l), j));
-      const float wca = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wca_l), j));
-      if (i >= R.i0 && i < R.i1) {
-        int ib;
-        float wfb, wcb;
-        sample_axis<WF>((float)i, R.gb, R.cb, hib, ib, wfb, wcb);
-        const uint32_t vo = (uint32_t)(ib + 1) * es;
-        float v00, v01, v10, v11;
-        buf_pair_s(rs, vo, row, (const T*)nullptr, v00, v01);
-        buf_pair_s(rs, vo, row + Sa, (const T*)nullptr, v10, v11);
-        acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
-        acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
+      const bool two = j + 1 < cnt;
+      const uint32_t row0 = (uint32_t)__builtin_amdgcn_readlane((int)row_l, j);
+      const float wfa0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wfa_l), j));
+      const float wca0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wca_l), j));
+      const uint32_t row1 = (uint32_t)__builtin_amdgcn_readlane((int)row_l, j + 1);
+      const float wfa1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wfa_l), j + 1));
+      const float wca1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wca_l), j + 1));
+      const bool in0 = i >= R.i0 && i < R.i1;
+      const bool in1 = two && i + 1 >= R.i0 && i + 1 < R.i1;
+      int ib0, ib1;
+      float wfb0, wcb0, wfb1, wcb1;
+      sample_axis<WF>((float)i, R.gb, R.cb, hib, ib0, wfb0, wcb0);
+      sample_axis<WF>((float)(i + 1), R.gb, R.cb, hib, ib1, wfb1, wcb1);
+      const uint32_t vo0 = (uint32_t)(ib0 + 1) * es;
+      const uint32_t vo1 = (uint32_t)(ib1 + 1) * es;
+      float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;
+      float u00 = 0.f, u01 = 0.f, u10 = 0.f, u11 = 0.f;
+      if (in0) {
+        buf_pair_s(rs, vo0, row0, (const T*)nullptr, v00, v01);
+        buf_pair_s(rs, vo0, row0 + Sa, (const T*)nullptr, v10, v11);
+      }
+      if (in1) {
+        buf_pair_s(rs, vo1, row1, (const T*)nullptr, u00, u01);
+        buf_pair_s(rs, vo1, row1 + Sa, (const T*)nullptr, u10, u11);
+      }
+      if (in0) {
+        acc = __builtin_fmaf(wfa0, __builtin_fmaf(wfb0, v00, wcb0 * v01), acc);
+        acc = __builtin_fmaf(wca0, __builtin_fmaf(wfb0, v10, wcb0 * v11), acc);
+      }
+      if (in1) {
+        acc = __builtin_fmaf(wfa1, __builtin_fmaf(wfb1, u00, wcb1 * u01), acc);
+        acc = __builtin_fmaf(wca1, __builtin_fmaf(wfb1, u10, wcb1 * u11), acc);
       }
     }
   }
   return acc;
 }
 
+// One ray per lane. All 64 lanes of the wavefront call this together; a lane
+// whose pixel lies outside the detector (valid == false) takes part in the
+// wavefront-wide steps with an empty sample range and stores nothing.
 template <typename T, int WF, bool IDX64>
-__device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv) {
+__device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv, bool valid) {
   using Index = std::conditional_t<IDX64, long long, int>;
   RaySetup R;
   ray_setup(a.views + 12 * (size_t)view, a.G, iu, iv, R);
+  if (!valid) R.i1 = R.i0;
   const T* __restrict__ base = static_cast<const T*>(a.vol);
   float acc = 0.0f;
   float fi = (float)R.i0;
+  if constexpr (!IDX64) {
+    // row-uniform wavefront: every lane with samples shares m (0 or 1), ca
+    // and ga; the shared values are the first such lane's
+    const bool has = R.i1 > R.i0;
+    const uint64_t hv = __ballot(has);
+    bool uniform = false;
+    int lm = 2;
+    float lca = 0.0f, lga = 0.0f;
+    if (hv != 0) {
+      const int leader = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)hv) - 1);
+      lm = __builtin_amdgcn_readlane(R.m, leader);
+      lca = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, R.ca), leader));
+      lga = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, R.ga), leader));
+      uniform = lm != 2 && __ballot(has && (R.m != lm || R.ca != lca || R.ga != lga)) == 0;
+    }
+    if (uniform) {
+      const int lo = __builtin_amdgcn_readfirstlane(wave_min(has ? R.i0 : 0x7fffffff));
+      const int hi = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i1 : -1));
+      acc = fwd_loop_rowuniform<T, WF>(a, R, lm, lca, lga, lo, hi);
+      if (valid) a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
+      return;
+    }
+  }
   if (R.m != 2) {
     if constexpr (!IDX64) {
-      // row-uniform wavefront: every lane with samples shares m, ca and ga
-      const bool has = R.i1 > R.i0;
-      const uint64_t hv = __ballot(has);
-      bool uniform = false;
-      if (hv != 0) {
-        const int leader = __ffsll((unsigned long long)hv) - 1;
-        const int lm = __shfl(R.m, leader);
-        const float lca = __shfl(R.ca, leader), lga = __shfl(R.ga, leader);
-        uniform = __ballot(has && (R.m != lm || R.ca != lca || R.ga != lga)) == 0;
-      }
-      if (uniform && __builtin_amdgcn_readfirstlane(R.m) != 2) {
-        const int lo = __builtin_amdgcn_readfirstlane(wave_min(has ? R.i0 : 0x7fffffff));
-        const int hi = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i1 : -1));
-        acc = fwd_loop_rowuniform<T, WF>(a, R, lo, hi);
-      } else {
-        acc = fwd_loop_buf<T, WF>(a, R);
-      }
+      acc = fwd_loop_buf<T, WF>(a, R);
     } else {
       // transverse axes: ta (rows, strided) and 2 (contiguous pairs)
       const Index Sm = (Index)(R.m == 0 ? a.S0 : a.S1);
@@ -315,7 +348,7 @@ __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int 
       fi += 1.0f;
     }
   }
-  a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
+  if (valid) a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
 }
 
 template <typename T, int WF, bool IDX64>
@@ -328,7 +361,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
   const int rows = 64 >> k;
   const int iv = (tv << k) + (lane & ((1 << k) - 1));
   const int iu = tu * (4 * rows) + wave * rows + (lane >> k);
-  if (iu < a.n_u && iv < a.n_v) fwd_ray<T, WF, IDX64>(a, view, iu, iv);
+  const bool valid = iu < a.n_u && iv < a.n_v;
+  fwd_ray<T, WF, IDX64>(a, view, valid ? iu : 0, valid ? iv : 0, valid);
 }
 
 template <typename T, int WF, bool IDX64>
