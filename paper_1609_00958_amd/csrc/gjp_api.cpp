@@ -508,12 +508,13 @@ FwdTile tile_for(const gjp_geometry* g, int dtype) {
 }
 
 long long padded_elems(const int* n) {
-  return (long long)(n[0] + 2) * (long long)(n[1] + 2) * (long long)(n[2] + 2);
+  return (long long)(n[0] + 2) * (long long)(n[1] + 2) * gjp::padded_pitch(n[2]);
 }
 
 void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* padded,
                    float* sino, const FwdTile& tile, FwdArgs& a) {
-  const long long p2 = g->n[2] + 2, p1 = g->n[1] + 2;
+  (void)padded;
+  const long long p2 = gjp::padded_pitch(g->n[2]), p1 = g->n[1] + 2;
   a.S1 = p2;
   a.S0 = p1 * p2;
   a.G = g->gg;
@@ -528,26 +529,37 @@ void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* pad
   a.tiles_v = (g->n_v + tile_v - 1) / tile_v;
   a.tiles_u = (g->n_u + tile_u - 1) / tile_u;
   a.tiles_per_view = a.tiles_v * a.tiles_u;
-  a.vol = padded;
 }
 
-// 32-bit buffer addressing needs the padded volume below 4 GiB and the plane
-// stride within 24-bit multiplies; otherwise the kernels use 64-bit offsets.
+// Bytes of one pair copy (two values per padded element), rounded up so that
+// copy B starts 256-byte aligned after copy A.
+unsigned long long copy_bytes(const int* n, int dtype) {
+  const unsigned long long b =
+      (unsigned long long)padded_elems(n) * 2ull * gjp::dtype_size(dtype);
+  return (b + 255ull) & ~255ull;
+}
+
+// The per-lane sampling loop addresses both pair copies with 32-bit offsets
+// and 24-bit row multiplies; larger copies take 64-bit pointer arithmetic.
 bool needs_idx64(const int* n, int dtype) {
-  const unsigned long long es = gjp::dtype_size(dtype);
-  const unsigned long long bytes = (unsigned long long)padded_elems(n) * es;
-  const unsigned long long s0 = (unsigned long long)(n[1] + 2) * (n[2] + 2) * es;
-  return bytes >= (1ull << 32) || s0 >= (1ull << 23);
+  const unsigned long long pe = 2ull * gjp::dtype_size(dtype);
+  const unsigned long long s0 = (unsigned long long)(n[1] + 2) * gjp::padded_pitch(n[2]) * pe;
+  return 2 * copy_bytes(n, dtype) >= (1ull << 32) || s0 >= (1ull << 23);
 }
 
-void set_padded(FwdArgs& a, const void* padded, int dtype, const int* n) {
-  a.vol_base = padded;
-  a.vol_bytes = (unsigned long long)padded_elems(n) * gjp::dtype_size(dtype);
+// The row-uniform loop addresses one block of 64 planes and 66 rows with
+// 32-bit offsets from its base, whichever axis drives.
+bool block_fits_32bit(const int* n, int dtype) {
+  const unsigned long long pe = 2ull * gjp::dtype_size(dtype);
+  const unsigned long long s1 = (unsigned long long)gjp::padded_pitch(n[2]) * pe;
+  const unsigned long long s0 = (unsigned long long)(n[1] + 2) * s1;
+  return 66ull * (s0 + s1) < (1ull << 32);
 }
 
-const void* padded_origin(const void* padded, int dtype, const FwdArgs& a) {
-  const size_t es = gjp::dtype_size(dtype);
-  return static_cast<const char*>(padded) + (size_t)(a.S0 + a.S1 + 1) * es;
+void set_padded(FwdArgs& a, void* copies, int dtype, const int* n) {
+  a.copy_bytes = copy_bytes(n, dtype);
+  a.vol_a = copies;
+  a.vol_b = static_cast<const char*>(copies) + a.copy_bytes;
 }
 
 gjp_status validate_fwd(const gjp_geometry* g, const void* d_vol, int32_t dtype,
@@ -567,15 +579,16 @@ gjp_status forward_with_tile(const gjp_geometry* g, const void* d_vol, int32_t d
   const float* d_proj = nullptr;
   int st = gjp::geometry_device(g, &d_views, &d_proj);
   if (st != GJP_OK) return (gjp_status)st;
-  const long long pe = padded_elems(g->n);
-  const size_t bytes = (size_t)pe * gjp::dtype_size(dtype);
+  if (!block_fits_32bit(g->n, dtype))
+    return fail(GJP_EUNSUPPORTED, "forward: volume planes too large for 32-bit block offsets");
   void* padded = nullptr;
-  GJP_HIP(scratch_alloc(&padded, bytes, s), "forward: padded volume");
+  GJP_HIP(scratch_alloc(&padded, (size_t)(2 * copy_bytes(g->n, dtype)), s),
+          "forward: padded pair copies");
   FwdArgs a;
   fill_fwd_args(g, d_views, nullptr, d_sino, tile, a);
-  a.vol = padded_origin(padded, dtype, a);
   set_padded(a, padded, dtype, g->n);
-  st = gjp::launch_pad(d_vol, padded, dtype, g->n, s);
+  st = gjp::launch_pad(d_vol, const_cast<void*>(a.vol_a), const_cast<void*>(a.vol_b), dtype,
+                       g->n, s);
   if (st == GJP_OK)
     st = gjp::launch_forward(a, dtype, g->weight, needs_idx64(g->n, dtype), g->n_views, s);
   const hipError_t fe = hipFreeAsync(padded, s);
@@ -670,7 +683,8 @@ extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sin
   const float* d_proj = nullptr;
   int st = gjp::geometry_device(g, &d_views, &d_proj);
   if (st != GJP_OK) return (gjp_status)st;
-  const size_t per_view = (size_t)g->n_u * g->n_v;
+  const size_t per_view =
+      (size_t)g->n_u * (size_t)(g->separable ? g->n_v + gjp::kColumnPad : g->n_v);
   const size_t entry = (g->separable ? 1 : 2) * sizeof(float4);
   const size_t col_entry = g->separable ? sizeof(float4) : 0;
   const size_t budget = (size_t)512 << 20;
@@ -781,9 +795,10 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
   for (int i = 0; i < n; ++i) {
     P->ids.push_back(g[i]->id);
     P->dtypes.push_back(dtypes[i]);
-    const long long pe = padded_elems(g[i]->n);
+    if (!block_fits_32bit(g[i]->n, dtypes[i]))
+      return fail(GJP_EUNSUPPORTED, "batched: volume planes too large for 32-bit block offsets");
     pad_off[i] = pad_bytes;
-    pad_bytes += ((size_t)pe * gjp::dtype_size(dtypes[i]) + 255) & ~(size_t)255;
+    pad_bytes += (size_t)(2 * copy_bytes(g[i]->n, dtypes[i]));
   }
   GJP_HIP(hipMalloc(&P->padded_all, pad_bytes), "batched: padded volumes");
   // work items: instances ordered by cost per item (longest first), then view, tile
@@ -805,7 +820,6 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
     t2.remap = 0;
     fill_fwd_args(g[i], d_views, nullptr, nullptr, t2, I.a);
     I.padded = static_cast<char*>(P->padded_all) + pad_off[i];
-    I.a.vol = padded_origin(I.padded, dtypes[i], I.a);
     set_padded(I.a, I.padded, dtypes[i], g[i]->n);
     I.n_views = g[i]->n_views;
     I.dtype = dtypes[i];

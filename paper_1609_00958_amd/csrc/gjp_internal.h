@@ -51,6 +51,10 @@ struct TimedLaunch {
 TimedLaunch timing_begin(const char* name, hipStream_t s);
 void timing_end(const char* name, TimedLaunch& t, hipStream_t s);
 
+// Empty entries after each detector column in the column-form ray table
+// (lets the adjoint read fixed-length candidate lists past a column's end).
+constexpr int kColumnPad = 8;
+
 // Launch configuration of the forward kernel.
 struct FwdTile {
   int tile_v_log2 = 6;  // detector pixels along v per wavefront row (64, 32, 16)
@@ -59,13 +63,13 @@ struct FwdTile {
 
 // Arguments of one forward launch (one volume, a range of views).
 struct FwdArgs {
-  const void* vol;      // padded volume, element (1,1,1) of the padded array
-  const void* vol_base; // padded volume, element (0,0,0)
-  unsigned long long vol_bytes;  // size of the padded volume in bytes
+  const void* vol_a;    // pair copy A (pairs along axis 1), padded element (0,0,0)
+  const void* vol_b;    // pair copy B (pairs along axis 0), padded element (0,0,0)
+  unsigned long long copy_bytes;  // bytes of one pair copy
   float* sino;          // sinogram of the whole geometry
   const double* views;  // device, n_views x 12 grid units
   GridGeom G;
-  long long S0, S1;     // padded strides in elements
+  long long S0, S1;     // padded strides in pair elements
   int n_u, n_v;
   int tile_v_log2;
   int tiles_v, tiles_u, tiles_per_view;
@@ -76,7 +80,8 @@ struct FwdArgs {
 int geometry_device(const gjp_geometry* g, const double** views, const float** proj);
 
 // Launchers (gjp_kernels.hip). Return a gjp_status.
-int launch_pad(const void* src, void* dst, int dtype, const int n[3], hipStream_t s);
+int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int n[3],
+               hipStream_t s);
 int launch_zero_ints(int* p, int n, hipStream_t s);
 int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,
                    hipStream_t s);
@@ -91,7 +96,7 @@ int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4
 struct BatchInst {
   FwdArgs a;
   const void* src;      // caller volume (unpadded)
-  void* padded;         // plan-owned padded copy
+  void* padded;         // plan-owned pair copies A and B (A at the start)
   int n_views;
   int dtype, weight, idx64;
   long long padded_elems;

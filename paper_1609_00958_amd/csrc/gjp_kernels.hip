@@ -35,30 +35,91 @@ struct f16_t {
   uint16_t bits;
 };
 
-typedef float f2a4 __attribute__((ext_vector_type(2), aligned(4)));
-typedef uint32_t u32a2 __attribute__((aligned(2)));
+// ---------------------------------------------------------------------------
+// Pair layout of the zero-padded volume. The padded grid has P0 x P1 x P2
+// elements (P0 = n0 + 2, P1 = n1 + 2, P2 = padded_pitch(n2)); padded index k
+// holds voxel k - 1 and the border holds zeros. Copy A stores at (x, y, z) the
+// pair (v(x, y, z), v(x, y + 1, z)), copy B the pair (v(x, y, z), v(x + 1, y,
+// z)), zero past the padded grid. A sample driven by axis 0 finds its four
+// in-plane neighbours (rows y, y + 1 at z, z + 1) in copy A as two adjacent
+// pairs: one 16-byte (FP32) or 8-byte (16-bit) load. A sample driven by axis 1
+// reads copy B the same way; one driven by axis 2 reads two pairs of copy A.
+// The address unit handles an irregular 16-byte load per lane at the rate of
+// an irregular 4-byte one, so one wide load per sample halves its work
+// against two row-pair loads.
+// ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void load_pair(const float* p, float& x0, float& x1) {
-  const f2a4 v = *reinterpret_cast<const f2a4*>(p);
-  x0 = v.x;
-  x1 = v.y;
+// Neighbours of one sample: rows a, a + 1 of the in-plane transverse axis at
+// the axis-2 positions z, z + 1.
+struct Quad {
+  float a0z0, a1z0, a0z1, a1z1;
+};
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef uint32_t u2a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef float f2a8 __attribute__((ext_vector_type(2), aligned(8)));
+typedef uint32_t u1a4 __attribute__((aligned(4)));
+
+__device__ __forceinline__ Quad widen4(u2v d, const bf16_t*) {
+  return {__uint_as_float(d.x << 16), __uint_as_float(d.x & 0xffff0000u),
+          __uint_as_float(d.y << 16), __uint_as_float(d.y & 0xffff0000u)};
 }
-__device__ __forceinline__ void load_pair(const bf16_t* p, float& x0, float& x1) {
-  const uint32_t u = *reinterpret_cast<const u32a2*>(p);
+__device__ __forceinline__ Quad widen4(u2v d, const f16_t*) {
+  typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+  const h4v h = __builtin_bit_cast(h4v, d);
+  return {(float)h.x, (float)h.y, (float)h.z, (float)h.w};
+}
+__device__ __forceinline__ void widen2(uint32_t u, const bf16_t*, float& x0, float& x1) {
   x0 = __uint_as_float(u << 16);
   x1 = __uint_as_float(u & 0xffff0000u);
 }
-__device__ __forceinline__ void load_pair(const f16_t* p, float& x0, float& x1) {
-  const uint32_t u = *reinterpret_cast<const u32a2*>(p);
-  x0 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
-  x1 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+__device__ __forceinline__ void widen2(uint32_t u, const f16_t*, float& x0, float& x1) {
+  typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+  const h2v h = __builtin_bit_cast(h2v, u);
+  x0 = (float)h.x;
+  x1 = (float)h.y;
 }
-__device__ __forceinline__ float load_one(const float* p) { return *p; }
-__device__ __forceinline__ float load_one(const bf16_t* p) {
-  return __uint_as_float((uint32_t)p->bits << 16);
+
+// Two adjacent pair elements at byte offset voff + soff of a buffer resource.
+__device__ __forceinline__ Quad buf_quad(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                         const float*) {
+  const f4v v = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  return {v.x, v.y, v.z, v.w};
 }
-__device__ __forceinline__ float load_one(const f16_t* p) {
-  return (float)__builtin_bit_cast(_Float16, p->bits);
+template <typename T>
+__device__ __forceinline__ Quad buf_quad(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                         const T* t) {
+  return widen4(__builtin_bit_cast(u2v, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0)), t);
+}
+// The same through a plain pointer to the first pair (64-bit addressing).
+__device__ __forceinline__ Quad ptr_quad(const float* p) {
+  const f4a8 v = *reinterpret_cast<const f4a8*>(p);
+  return {v.x, v.y, v.z, v.w};
+}
+template <typename T>
+__device__ __forceinline__ Quad ptr_quad(const T* p) {
+  return widen4(__builtin_bit_cast(u2v, *reinterpret_cast<const u2a4*>(p)), p);
+}
+// One pair element through a plain pointer.
+__device__ __forceinline__ void ptr_pair(const float* p, float& x0, float& x1) {
+  const f2a8 v = *reinterpret_cast<const f2a8*>(p);
+  x0 = v.x;
+  x1 = v.y;
+}
+template <typename T>
+__device__ __forceinline__ void ptr_pair(const T* p, float& x0, float& x1) {
+  widen2(*reinterpret_cast<const u1a4*>(p), p, x0, x1);
+}
+
+// acc += wfa (wfb v(a, z) + wcb v(a, z+1)) + wca (wfb v(a+1, z) + wcb v(a+1, z+1)),
+// as two fused steps in this order (Eq. 13 with the weights of Eqs. 10-12).
+__device__ __forceinline__ float accumulate4(float acc, float wfa, float wca, float wfb,
+                                             float wcb, const Quad& q) {
+  acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, q.a0z0, wcb * q.a0z1), acc);
+  acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, q.a1z0, wcb * q.a1z1), acc);
+  return acc;
 }
 
 // Consecutive workgroup ids are dispatched round-robin over the 8 XCDs (each
@@ -71,62 +132,60 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
 }
 
 // ---------------------------------------------------------------------------
-// Zero-padded copy: dst has (n0+2) x (n1+2) x (n2+2) elements.
+// Zero-padded pair copies A and B (layout above) of an n0 x n1 x n2 volume of
+// E-sized elements. One thread per padded element (x, y, z).
 // ---------------------------------------------------------------------------
 template <typename E>
-__global__ __launch_bounds__(256) void pad_kernel(const E* __restrict__ src, E* __restrict__ dst,
-                                                  int n0, int n1, int n2) {
+__device__ __forceinline__ E padded_value(const E* __restrict__ src, int n0, int n1, int n2,
+                                          int x, int y, int z) {
+  if (x >= 1 && x <= n0 && y >= 1 && y <= n1 && z >= 1 && z <= n2)
+    return src[((size_t)(x - 1) * n1 + (y - 1)) * n2 + (z - 1)];
+  return (E)0;
+}
+
+template <typename E>
+__device__ __forceinline__ void pad_pair_element(const E* __restrict__ src, E* __restrict__ A,
+                                                 E* __restrict__ B, int n0, int n1, int n2,
+                                                 long long e, int x, int y, int z) {
+  const E v = padded_value(src, n0, n1, n2, x, y, z);
+  A[2 * e] = v;
+  A[2 * e + 1] = padded_value(src, n0, n1, n2, x, y + 1, z);
+  B[2 * e] = v;
+  B[2 * e + 1] = padded_value(src, n0, n1, n2, x + 1, y, z);
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void pad_kernel(const E* __restrict__ src, E* __restrict__ A,
+                                                  E* __restrict__ B, int n0, int n1, int n2) {
   const int z = blockIdx.x * 256 + threadIdx.x;
   const int y = blockIdx.y;
   const int x = blockIdx.z;
-  const int p2 = n2 + 2;
+  const int p2 = (int)padded_pitch(n2);
   if (z >= p2) return;
-  E val = 0;
-  if (x >= 1 && x <= n0 && y >= 1 && y <= n1 && z >= 1 && z <= n2)
-    val = src[((size_t)(x - 1) * n1 + (y - 1)) * n2 + (z - 1)];
-  dst[((size_t)x * (n1 + 2) + y) * p2 + z] = val;
+  const long long e = ((long long)x * (n1 + 2) + y) * p2 + z;
+  pad_pair_element(src, A, B, n0, n1, n2, e, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
 // Forward projection of one ray (Algorithm 1).
 // ---------------------------------------------------------------------------
-typedef float f2v __attribute__((ext_vector_type(2)));
 
-// Row pair (z, z+1) at byte offset `off` of the padded volume, widened to FP32.
-__device__ __forceinline__ void buf_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, const float*,
-                                         float& x0, float& x1) {
-  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-  x0 = v.x;
-  x1 = v.y;
-}
-__device__ __forceinline__ void buf_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, const bf16_t*,
-                                         float& x0, float& x1) {
-  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-  x0 = __uint_as_float(u << 16);
-  x1 = __uint_as_float(u & 0xffff0000u);
-}
-__device__ __forceinline__ void buf_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, const f16_t*,
-                                         float& x0, float& x1) {
-  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-  x0 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
-  x1 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
-}
-
-// Sampling loop for driving axes 0 and 1 on a padded volume below 4 GiB:
-// 32-bit byte offsets into a buffer resource, two samples per iteration so
-// that four row-pair loads are in flight per lane.
+// Sampling loop for driving axes 0 and 1 with 32-bit offsets from copy A
+// (copy B follows it; both below 4 GiB together), two samples per iteration so
+// that two wide loads are in flight per lane. The lanes of a wavefront may
+// differ in m, so the copy is chosen by offset, not by resource.
 template <typename T, int WF>
 __device__ __forceinline__ float fwd_loop_buf(const FwdArgs& a, const RaySetup& R) {
-  constexpr uint32_t es = sizeof(T);
+  constexpr uint32_t pe = 2 * sizeof(T);
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<void*>(a.vol_base), (short)0, (int)(uint32_t)a.vol_bytes, 0x00020000);
-  const uint32_t Sm = (uint32_t)(R.m == 0 ? a.S0 : a.S1) * es;
-  const int Sa = (int)((R.m == 0 ? a.S1 : a.S0) * (long long)es);
-  const float h0 = a.G.hi[0], h1 = a.G.hi[1];
-  const float hia = (R.m == 0) ? h1 : h0;
+      const_cast<void*>(a.vol_a), (short)0, (int)(uint32_t)(2 * a.copy_bytes), 0x00020000);
+  const uint32_t Sm = (uint32_t)(R.m == 0 ? a.S0 : a.S1) * pe;
+  const int Sa = (int)((R.m == 0 ? a.S1 : a.S0) * (long long)pe);
+  const float hia = (R.m == 0) ? a.G.hi[1] : a.G.hi[0];
   const float hib = a.G.hi[2];
-  // padded frame: (plane + 1, row + 1, col + 1)
-  uint32_t off_m = (uint32_t)(R.i0 + 1) * Sm + (uint32_t)Sa + es;
+  // padded frame: (plane + 1, row + 1, col + 1) of the ray's copy
+  uint32_t off_m = (R.m == 0 ? 0u : (uint32_t)a.copy_bytes) + (uint32_t)(R.i0 + 1) * Sm +
+                   (uint32_t)Sa + pe;
   float acc = 0.0f;
   float fi = (float)R.i0;
   int i = R.i0;
@@ -137,17 +196,12 @@ __device__ __forceinline__ float fwd_loop_buf(const FwdArgs& a, const RaySetup& 
     sample_axis<WF>(fi, R.gb, R.cb, hib, ib0, wfb0, wcb0);
     sample_axis<WF>(fi + 1.0f, R.ga, R.ca, hia, ia1, wfa1, wca1);
     sample_axis<WF>(fi + 1.0f, R.gb, R.cb, hib, ib1, wfb1, wcb1);
-    const uint32_t o0 = (uint32_t)__mul24(ia0, Sa) + off_m + (uint32_t)ib0 * es;
-    const uint32_t o1 = (uint32_t)__mul24(ia1, Sa) + off_m + Sm + (uint32_t)ib1 * es;
-    float v00, v01, v10, v11, u00, u01, u10, u11;
-    buf_pair(rs, o0, (const T*)nullptr, v00, v01);
-    buf_pair(rs, o0 + (uint32_t)Sa, (const T*)nullptr, v10, v11);
-    buf_pair(rs, o1, (const T*)nullptr, u00, u01);
-    buf_pair(rs, o1 + (uint32_t)Sa, (const T*)nullptr, u10, u11);
-    acc = __builtin_fmaf(wfa0, __builtin_fmaf(wfb0, v00, wcb0 * v01), acc);
-    acc = __builtin_fmaf(wca0, __builtin_fmaf(wfb0, v10, wcb0 * v11), acc);
-    acc = __builtin_fmaf(wfa1, __builtin_fmaf(wfb1, u00, wcb1 * u01), acc);
-    acc = __builtin_fmaf(wca1, __builtin_fmaf(wfb1, u10, wcb1 * u11), acc);
+    const uint32_t o0 = (uint32_t)__mul24(ia0, Sa) + off_m + (uint32_t)ib0 * pe;
+    const uint32_t o1 = (uint32_t)__mul24(ia1, Sa) + off_m + Sm + (uint32_t)ib1 * pe;
+    const Quad q0 = buf_quad(rs, o0, 0, (const T*)nullptr);
+    const Quad q1 = buf_quad(rs, o1, 0, (const T*)nullptr);
+    acc = accumulate4(acc, wfa0, wca0, wfb0, wcb0, q0);
+    acc = accumulate4(acc, wfa1, wca1, wfb1, wcb1, q1);
     fi += 2.0f;
     off_m += 2 * Sm;
   }
@@ -156,34 +210,33 @@ __device__ __forceinline__ float fwd_loop_buf(const FwdArgs& a, const RaySetup& 
     float wfa0, wca0, wfb0, wcb0;
     sample_axis<WF>(fi, R.ga, R.ca, hia, ia0, wfa0, wca0);
     sample_axis<WF>(fi, R.gb, R.cb, hib, ib0, wfb0, wcb0);
-    const uint32_t o0 = (uint32_t)__mul24(ia0, Sa) + off_m + (uint32_t)ib0 * es;
-    float v00, v01, v10, v11;
-    buf_pair(rs, o0, (const T*)nullptr, v00, v01);
-    buf_pair(rs, o0 + (uint32_t)Sa, (const T*)nullptr, v10, v11);
-    acc = __builtin_fmaf(wfa0, __builtin_fmaf(wfb0, v00, wcb0 * v01), acc);
-    acc = __builtin_fmaf(wca0, __builtin_fmaf(wfb0, v10, wcb0 * v11), acc);
+    const uint32_t o0 = (uint32_t)__mul24(ia0, Sa) + off_m + (uint32_t)ib0 * pe;
+    acc = accumulate4(acc, wfa0, wca0, wfb0, wcb0, buf_quad(rs, o0, 0, (const T*)nullptr));
   }
   return acc;
 }
 
-// Row pair at (scalar byte offset + lane byte offset), for the row-uniform loop.
-__device__ __forceinline__ void buf_pair_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                           const float*, float& x0, float& x1) {
-  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-  x0 = v.x;
-  x1 = v.y;
-}
-__device__ __forceinline__ void buf_pair_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                           const bf16_t*, float& x0, float& x1) {
-  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-  x0 = __uint_as_float(u << 16);
-  x1 = __uint_as_float(u & 0xffff0000u);
-}
-__device__ __forceinline__ void buf_pair_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                           const f16_t*, float& x0, float& x1) {
-  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-  x0 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u & 0xffffu));
-  x1 = (float)__builtin_bit_cast(_Float16, (uint16_t)(u >> 16));
+// The same with 64-bit element indices (pair copies of 4 GiB or more).
+template <typename T, int WF>
+__device__ __forceinline__ float fwd_loop_ptr(const FwdArgs& a, const RaySetup& R) {
+  const T* base = static_cast<const T*>(R.m == 0 ? a.vol_a : a.vol_b);
+  const long long Sm = (R.m == 0 ? a.S0 : a.S1), Sa = (R.m == 0 ? a.S1 : a.S0);
+  const float hia = (R.m == 0) ? a.G.hi[1] : a.G.hi[0];
+  const float hib = a.G.hi[2];
+  long long off_m = (long long)(R.i0 + 1) * Sm + Sa + 1;
+  float acc = 0.0f;
+  float fi = (float)R.i0;
+  for (int i = R.i0; i < R.i1; ++i) {
+    int ia, ib;
+    float wfa, wca, wfb, wcb;
+    sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
+    sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
+    const long long e = off_m + (long long)ia * Sa + ib;
+    acc = accumulate4(acc, wfa, wca, wfb, wcb, ptr_quad(base + 2 * e));
+    fi += 1.0f;
+    off_m += Sm;
+  }
+  return acc;
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -197,24 +250,50 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// Sampling loop for a wavefront whose rays all share the driving axis (0 or
+// One plane of the row-uniform loop. q = {row byte offset, wfa, wca} of the
+// plane (wave-uniform); CHECK zeroes the axis-2 weights of lanes whose sample
+// range excludes the plane (the load stays in bounds: the row is inside the
+// copy and the axis-2 coordinate is clamped). A zeroed plane adds +-0, so the
+// lane's sum is unchanged.
+template <typename T, int WF, bool CHECK>
+__device__ __forceinline__ void ru_plane(__amdgpu_buffer_rsrc_t rs, const float4 q, int i,
+                                         const RaySetup& R, float hib, float& acc) {
+  constexpr uint32_t pe = 2 * sizeof(T);
+  int ib;
+  float wfb, wcb;
+  sample_axis<WF>((float)i, R.gb, R.cb, hib, ib, wfb, wcb);
+  if (CHECK) {
+    const bool in = i >= R.i0 && i < R.i1;
+    wfb = in ? wfb : 0.0f;
+    wcb = in ? wcb : 0.0f;
+  }
+  const uint32_t vo = (uint32_t)(ib + 1) * pe + __float_as_uint(q.x);
+  acc = accumulate4(acc, q.y, q.z, wfb, wcb, buf_quad(rs, vo, 0, (const T*)nullptr));
+}
+
+// Sampling loop for a wavefront whose rays all share the driving axis m (0 or
 // 1) and the in-plane coefficients (ca, ga): the row coordinate, its weights
 // and the row offset of every plane are the same for all lanes. Lane l
-// evaluates them for plane base + l of each block of 64 planes, and the loop
-// broadcasts plane j's values with readlane; lanes only evaluate the axis-2
-// coordinate. Each lane accumulates exactly the terms, in the same order and
-// with the same arithmetic, as fwd_loop_buf, so the results are identical.
-//
-// m, ca and ga are the shared (wave-uniform) values; every one of the 64 lanes
-// must be active, since each computes the row data of one plane.
+// evaluates them for plane base + l of each block of 64 planes and stores
+// them in the wavefront's LDS slots; each plane reads its slot back as a
+// broadcast, so lanes only evaluate the axis-2 coordinate. Each block reads
+// through a buffer resource based at its first plane and lowest row, so the
+// offsets stay 32-bit for any volume size. Planes in [mid_lo, mid_hi) lie
+// inside every sampling lane's range and skip the range test. Each lane
+// accumulates exactly the terms, in the same order and with the same
+// arithmetic, as fwd_loop_buf, so the sums are identical (up to the sign of a
+// zero). Every one of the 64 lanes must take part; the sums of lanes without
+// samples are meaningless and must be discarded by the caller.
 template <typename T, int WF>
 __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const RaySetup& R, int m,
-                                                     float ca, float ga, int lo, int hi) {
-  constexpr uint32_t es = sizeof(T);
-  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<void*>(a.vol_base), (short)0, (int)(uint32_t)a.vol_bytes, 0x00020000);
-  const uint32_t Sm = (uint32_t)(m == 0 ? a.S0 : a.S1) * es;
-  const uint32_t Sa = (uint32_t)((m == 0 ? a.S1 : a.S0) * (long long)es);
+                                                     float ca, float ga, int lo, int hi,
+                                                     int mid_lo, int mid_hi) {
+  constexpr uint32_t pe = 2 * sizeof(T);
+  __shared__ float4 s_planes[4][64];
+  float4* slots = s_planes[threadIdx.x >> 6];
+  const char* copy = static_cast<const char*>(m == 0 ? a.vol_a : a.vol_b);
+  const unsigned long long Sm = (unsigned long long)(m == 0 ? a.S0 : a.S1) * pe;
+  const unsigned long long Sa = (unsigned long long)(m == 0 ? a.S1 : a.S0) * pe;
   const float hia = (m == 0) ? a.G.hi[1] : a.G.hi[0];
   const float hib = a.G.hi[2];
   const int lane = (int)(threadIdx.x & 63);
@@ -223,48 +302,41 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
     int ia_l;
     float wfa_l, wca_l;
     sample_axis<WF>((float)(base + lane), ga, ca, hia, ia_l, wfa_l, wca_l);
-    // byte offset of (plane + 1, row + 1, 0) in the padded volume
-    const uint32_t row_l = (uint32_t)(base + lane + 1) * Sm + (uint32_t)(ia_l + 1) * Sa;
+    // block origin: padded plane base + 1, padded row ia_min + 1, column 0
+    const int ia_min = __builtin_amdgcn_readfirstlane(wave_min(ia_l));
+    const unsigned long long org = (unsigned long long)(base + 1) * Sm +
+                                   (unsigned long long)(ia_min + 1) * Sa;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(copy + org), (short)0,
+        (int)(uint32_t)min(a.copy_bytes - org, 0xffffffffull), 0x00020000);
+    const uint32_t row_l = (uint32_t)((unsigned long long)lane * Sm +
+                                      (unsigned long long)(ia_l - ia_min) * Sa);
+    slots[lane] = make_float4(__uint_as_float(row_l), wfa_l, wca_l, 0.0f);
+    __builtin_amdgcn_wave_barrier();
     const int cnt = min(64, hi - base);
-    // two planes per iteration: both planes' loads are issued before either
-    // is consumed; each plane still contributes in order and only inside the
-    // lane's own sample range
-    for (int j = 0; j < cnt; j += 2) {
+    const int j0 = min(max(mid_lo - base, 0), cnt);
+    const int j1 = min(max(mid_hi - base, j0), cnt);
+    int j = 0;
+    for (; j < j0; ++j) ru_plane<T, WF, true>(rs, slots[j], base + j, R, hib, acc);
+    // two planes per iteration: both wide loads are issued first
+    for (; j + 1 < j1; j += 2) {
+      const float4 q0 = slots[j], q1 = slots[j + 1];
       const int i = base + j;
-      const bool two = j + 1 < cnt;
-      const uint32_t row0 = (uint32_t)__builtin_amdgcn_readlane((int)row_l, j);
-      const float wfa0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wfa_l), j));
-      const float wca0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wca_l), j));
-      const uint32_t row1 = (uint32_t)__builtin_amdgcn_readlane((int)row_l, j + 1);
-      const float wfa1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wfa_l), j + 1));
-      const float wca1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wca_l), j + 1));
-      const bool in0 = i >= R.i0 && i < R.i1;
-      const bool in1 = two && i + 1 >= R.i0 && i + 1 < R.i1;
       int ib0, ib1;
       float wfb0, wcb0, wfb1, wcb1;
       sample_axis<WF>((float)i, R.gb, R.cb, hib, ib0, wfb0, wcb0);
       sample_axis<WF>((float)(i + 1), R.gb, R.cb, hib, ib1, wfb1, wcb1);
-      const uint32_t vo0 = (uint32_t)(ib0 + 1) * es;
-      const uint32_t vo1 = (uint32_t)(ib1 + 1) * es;
-      float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;
-      float u00 = 0.f, u01 = 0.f, u10 = 0.f, u11 = 0.f;
-      if (in0) {
-        buf_pair_s(rs, vo0, row0, (const T*)nullptr, v00, v01);
-        buf_pair_s(rs, vo0, row0 + Sa, (const T*)nullptr, v10, v11);
-      }
-      if (in1) {
-        buf_pair_s(rs, vo1, row1, (const T*)nullptr, u00, u01);
-        buf_pair_s(rs, vo1, row1 + Sa, (const T*)nullptr, u10, u11);
-      }
-      if (in0) {
-        acc = __builtin_fmaf(wfa0, __builtin_fmaf(wfb0, v00, wcb0 * v01), acc);
-        acc = __builtin_fmaf(wca0, __builtin_fmaf(wfb0, v10, wcb0 * v11), acc);
-      }
-      if (in1) {
-        acc = __builtin_fmaf(wfa1, __builtin_fmaf(wfb1, u00, wcb1 * u01), acc);
-        acc = __builtin_fmaf(wca1, __builtin_fmaf(wfb1, u10, wcb1 * u11), acc);
-      }
+      const uint32_t vo0 = (uint32_t)(ib0 + 1) * pe + __float_as_uint(q0.x);
+      const uint32_t vo1 = (uint32_t)(ib1 + 1) * pe + __float_as_uint(q1.x);
+      const Quad u0 = buf_quad(rs, vo0, 0, (const T*)nullptr);
+      const Quad u1 = buf_quad(rs, vo1, 0, (const T*)nullptr);
+      acc = accumulate4(acc, q0.y, q0.z, wfb0, wcb0, u0);
+      acc = accumulate4(acc, q1.y, q1.z, wfb1, wcb1, u1);
     }
+    for (; j < j1; ++j) ru_plane<T, WF, false>(rs, slots[j], base + j, R, hib, acc);
+    for (; j < cnt; ++j) ru_plane<T, WF, true>(rs, slots[j], base + j, R, hib, acc);
+    // every lane has read the slots before the next block rewrites them
+    __builtin_amdgcn_wave_barrier();
   }
   return acc;
 }
@@ -274,77 +346,53 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
 // wavefront-wide steps with an empty sample range and stores nothing.
 template <typename T, int WF, bool IDX64>
 __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv, bool valid) {
-  using Index = std::conditional_t<IDX64, long long, int>;
   RaySetup R;
   ray_setup(a.views + 12 * (size_t)view, a.G, iu, iv, R);
   if (!valid) R.i1 = R.i0;
-  const T* __restrict__ base = static_cast<const T*>(a.vol);
   float acc = 0.0f;
-  float fi = (float)R.i0;
-  if constexpr (!IDX64) {
-    // row-uniform wavefront: every lane with samples shares m (0 or 1), ca
-    // and ga; the shared values are the first such lane's
-    const bool has = R.i1 > R.i0;
-    const uint64_t hv = __ballot(has);
-    bool uniform = false;
-    int lm = 2;
-    float lca = 0.0f, lga = 0.0f;
-    if (hv != 0) {
-      const int leader = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)hv) - 1);
-      lm = __builtin_amdgcn_readlane(R.m, leader);
-      lca = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, R.ca), leader));
-      lga = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, R.ga), leader));
-      uniform = lm != 2 && __ballot(has && (R.m != lm || R.ca != lca || R.ga != lga)) == 0;
-    }
-    if (uniform) {
-      const int lo = __builtin_amdgcn_readfirstlane(wave_min(has ? R.i0 : 0x7fffffff));
-      const int hi = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i1 : -1));
-      acc = fwd_loop_rowuniform<T, WF>(a, R, lm, lca, lga, lo, hi);
-      if (valid) a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
-      return;
-    }
+  // row-uniform wavefront: every lane with samples shares m (0 or 1), ca and
+  // ga; the shared values are the first such lane's
+  const bool has = R.i1 > R.i0;
+  const uint64_t hv = __ballot(has);
+  bool uniform = false;
+  int lm = 2;
+  float lca = 0.0f, lga = 0.0f;
+  if (hv != 0) {
+    const int leader = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)hv) - 1);
+    lm = __builtin_amdgcn_readlane(R.m, leader);
+    lca = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, R.ca), leader));
+    lga = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, R.ga), leader));
+    uniform = lm != 2 && __ballot(has && (R.m != lm || R.ca != lca || R.ga != lga)) == 0;
   }
-  if (R.m != 2) {
-    if constexpr (!IDX64) {
+  if (uniform) {
+    const int lo = __builtin_amdgcn_readfirstlane(wave_min(has ? R.i0 : 0x7fffffff));
+    const int hi = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i1 : -1));
+    const int mid_lo = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i0 : -1));
+    const int mid_hi = __builtin_amdgcn_readfirstlane(wave_min(has ? R.i1 : 0x7fffffff));
+    acc = fwd_loop_rowuniform<T, WF>(a, R, lm, lca, lga, lo, hi, mid_lo, mid_hi);
+    if (!has) acc = 0.0f;
+  } else if (R.m != 2) {
+    if constexpr (!IDX64)
       acc = fwd_loop_buf<T, WF>(a, R);
-    } else {
-      // transverse axes: ta (rows, strided) and 2 (contiguous pairs)
-      const Index Sm = (Index)(R.m == 0 ? a.S0 : a.S1);
-      const Index Sa = (Index)(R.m == 0 ? a.S1 : a.S0);
-      const float hia = (R.m == 0) ? a.G.hi[1] : a.G.hi[0];
-      const float hib = a.G.hi[2];
-      Index off_m = (Index)R.i0 * Sm;
-      for (int i = R.i0; i < R.i1; ++i) {
-        int ia, ib;
-        float wfa, wca, wfb, wcb;
-        sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
-        sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
-        const Index off = off_m + (Index)ia * Sa + (Index)ib;
-        float v00, v01, v10, v11;
-        load_pair(base + off, v00, v01);
-        load_pair(base + off + Sa, v10, v11);
-        acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
-        acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
-        fi += 1.0f;
-        off_m += Sm;
-      }
-    }
+    else
+      acc = fwd_loop_ptr<T, WF>(a, R);
   } else {
-    // driving axis 2: both transverse axes strided, four single loads
-    const Index S0 = (Index)a.S0, S1 = (Index)a.S1;
+    // driving axis 2: transverse axes 0 (rows of copy A, stride S0) and 1
+    // (pairs of copy A); two pair loads per sample
+    const T* base = static_cast<const T*>(a.vol_a);
+    const long long S0 = a.S0, S1 = a.S1;
     const float hia = a.G.hi[0], hib = a.G.hi[1];
+    float fi = (float)R.i0;
     for (int i = R.i0; i < R.i1; ++i) {
       int ia, ib;
       float wfa, wca, wfb, wcb;
       sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
       sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
-      const Index off = (Index)i + (Index)ia * S0 + (Index)ib * S1;
-      const float v00 = load_one(base + off);
-      const float v01 = load_one(base + off + S1);
-      const float v10 = load_one(base + off + S0);
-      const float v11 = load_one(base + off + S0 + S1);
-      acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, v00, wcb * v01), acc);
-      acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, v10, wcb * v11), acc);
+      const long long e = (long long)(ia + 1) * S0 + (long long)(ib + 1) * S1 + (i + 1);
+      Quad q;
+      ptr_pair(base + 2 * e, q.a0z0, q.a0z1);
+      ptr_pair(base + 2 * (e + S0), q.a1z0, q.a1z1);
+      acc = accumulate4(acc, wfa, wca, wfb, wcb, q);
       fi += 1.0f;
     }
   }
@@ -378,8 +426,9 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
 // Adjoint pass 1: per-ray table for views [view0, view0 + n_chunk).
 // General layout, two float4 per ray: {m | i0 << 2 | i1 << 17, ca, ga, cb},
 // {gb, y * scale, 0, 0}. Column layout (see adj_gather_sep_kernel): one float4
-// per ray {m | i0 << 2 | i1 << 17, cb, gb, y * scale} and one per detector
-// column {m, ca, ga, 0}.
+// per ray {m | i0 << 2 | i1 << 17, cb, gb, y * scale}, each detector column's
+// rays followed by kColumnPad zero entries, and one float4 per detector column
+// {m, ca, ga, 0}.
 // mask[c] collects the driving axes that have samples in view view0 + c.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict__ views,
@@ -403,9 +452,12 @@ __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict
     const float y = sino[(size_t)(view0 + cv) * per_view + rem];
     const uint32_t mr = (uint32_t)R.m | ((uint32_t)R.i0 << 2) | ((uint32_t)R.i1 << 17);
     if (separable) {
-      table[r] = make_float4(__uint_as_float(mr), R.cb, R.gb, y * R.scale);
-      if (iv == 0)
+      float4* col = table + ((size_t)cv * n_u + iu) * (size_t)(n_v + kColumnPad);
+      col[iv] = make_float4(__uint_as_float(mr), R.cb, R.gb, y * R.scale);
+      if (iv == 0) {
         cols[(size_t)cv * n_u + iu] = make_float4(__uint_as_float((uint32_t)R.m), R.ca, R.ga, 0.0f);
+        for (int k = 0; k < kColumnPad; ++k) col[n_v + k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
     } else {
       table[2 * r] = make_float4(__uint_as_float(mr), R.ca, R.ga, R.cb);
       table[2 * r + 1] = make_float4(R.gb, y * R.scale, 0.0f, 0.0f);
@@ -614,35 +666,113 @@ __global__ __launch_bounds__(256) void adj_splat_kernel(
 // plane can lie within one voxel (wave-uniform); in each column the candidate
 // rays are the few whose axis-2 coordinate can reach the pair, an affine range
 // in the ray index (the detector's axis-2 direction keeps the projective
-// denominator independent of z). Each candidate sample is evaluated once, with
-// the forward's sample_axis, for both voxels; each voxel sums its
-// contributions in registers and is written once per launch. No LDS, no
-// barriers, no atomics.
+// denominator independent of z) whose length is bounded by a wave-uniform
+// count. Each candidate sample is evaluated once for both voxels; each voxel
+// sums its contributions in registers and is written once per launch. No LDS,
+// no barriers, no atomics.
+//
+// The table holds each detector column's rays followed by kColumnPad empty
+// entries (no samples, value 0), so a candidate list may run past the
+// column's end.
 // ---------------------------------------------------------------------------
+
+// Weights of one sample for the voxels z and z + 1 (zero unless the sample's
+// floor or floor + 1 is one of them). Linear: the tent 1 - |p - z| on the
+// clamped coordinate, which reproduces the forward's 1 - d and 1 - (1 - d)
+// (exact differences of nearby floats); other weights: the forward's floor
+// and complementary weights, selected by the floor's position.
+template <int WF>
+__device__ __forceinline__ void pair_weights(float fplane, float g, float c, float hz, float fz,
+                                             int z, float& b0, float& b1) {
+  if constexpr (WF == W_LINEAR) {
+    float p = __builtin_fmaf(fplane, g, c);
+    p = __builtin_amdgcn_fmed3f(p, -1.0f, hz);
+    const float s0 = p - fz;
+    const float s1 = s0 - 1.0f;
+    b0 = __builtin_fmaxf(1.0f - __builtin_fabsf(s0), 0.0f);
+    b1 = __builtin_fmaxf(1.0f - __builtin_fabsf(s1), 0.0f);
+  } else {
+    int ib;
+    float wfb, wcb;
+    sample_axis<WF>(fplane, g, c, hz, ib, wfb, wcb);
+    const int d = ib - z;  // the sample's floor relative to the pair
+    b0 = (d == 0) ? wfb : ((d == -1) ? wcb : 0.0f);
+    b1 = (d == 1) ? wfb : ((d == 0) ? wcb : 0.0f);
+  }
+}
+
+// NC candidate rays R[iv_lo .. iv_lo + NC): all loads first, then the sums.
+template <int WF, int NC>
+__device__ __forceinline__ void pair_candidates(const float4* __restrict__ R, int iv_lo, int plane,
+                                                float fplane, float hz, float fz, int z,
+                                                float& c0, float& c1) {
+  float4 rr[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) rr[k] = R[iv_lo + k];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const float4 r = rr[k];
+    const uint32_t mr = __float_as_uint(r.x);
+    const int i0 = (int)((mr >> 2) & 0x7fffu);
+    const int i1 = (int)(mr >> 17);
+    float b0, b1;
+    pair_weights<WF>(fplane, r.z, r.y, hz, fz, z, b0, b1);
+    const float wy = (plane >= i0 && plane < i1) ? r.w : 0.0f;
+    c0 = __builtin_fmaf(wy, b0, c0);
+    c1 = __builtin_fmaf(wy, b1, c1);
+  }
+}
+
+// Workgroup placement of the gather: a workgroup covers 4 rows (x, y .. y+3)
+// of 128 voxels along axis 2. Logical workgroup indices are ordered in tiles
+// of GTX x-planes by GTY row blocks (axis-2 blocks fastest), and each XCD
+// walks one contiguous range of them, so the workgroups resident on an XCD
+// cover a compact (x, y) region whose rays come from a few detector columns
+// per view: the ray table they read stays in that XCD's L2.
+constexpr int GTX = 16, GTY = 8;
+
+__host__ __device__ inline void gather_grid(const int* n, int& nzb, int& nyb, int& ntx, int& nty) {
+  nzb = (n[2] + 127) / 128;
+  nyb = (n[1] + 3) / 4;
+  ntx = (n[0] + GTX - 1) / GTX;
+  nty = (nyb + GTY - 1) / GTY;
+}
+
 template <int WF>
 __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
     const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
     const float4* __restrict__ rays, const float4* __restrict__ cols,
     const int* __restrict__ mask, int view0, int c0, int n_chunk, int accumulate,
     float* __restrict__ vol) {
+  int nzb, nyb, ntx, nty;
+  gather_grid(G.n, nzb, nyb, ntx, nty);
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t per_tile = (uint32_t)(GTX * GTY * nzb);
+  const int tile = (int)(L / per_tile);
+  const int w = (int)(L - (uint32_t)tile * per_tile);
+  const int zb = w % nzb;
+  const int iyb = (w / nzb) % GTY;
+  const int ix = w / (nzb * GTY);
+  const int x = (tile / nty) * GTX + ix;
+  const int yb = (tile % nty) * GTY + iyb;
+  if (x >= G.n[0] || yb >= nyb) return;
   // a lane owns the voxel pair (x, y, z) and (x, y, z + 1)
-  const int z = 2 * (blockIdx.x * 64 + (int)(threadIdx.x & 63));
-  const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int x = blockIdx.z;
+  const int z = 2 * (zb * 64 + (int)(threadIdx.x & 63));
+  const int y = yb * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (y >= G.n[1]) return;
   const bool zin = z < G.n[2];
   const float fx = (float)x, fy = (float)y, fz = (float)z;
   const float hx = G.hi[0], hy = G.hi[1], hz = G.hi[2];
   const float e = 0.002f;       // widened neighbourhood (voxels)
   const float margin = 0.05f;   // widened ranges (pixels)
-  constexpr int NC = 6;         // candidate rays loaded together per column
+  const int pitch = n_v + kColumnPad;  // table entries per detector column
   float acc0 = 0.0f, acc1 = 0.0f;
   for (int c = c0; c < c0 + n_chunk; ++c) {
     const int mk = mask[c];
     if (!mk) continue;
     const float* P = proj + 12 * (size_t)(view0 + c);
     const float4* C = cols + (size_t)c * n_u;
-    const float4* RY = rays + (size_t)c * n_u * n_v;
+    const float4* RY = rays + (size_t)c * n_u * pitch;
     for (int m = 0; m < 2; ++m) {
       if (!(mk & (1 << m))) continue;
       const int plane = (m == 0) ? x : y;
@@ -671,60 +801,56 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
         sample_axis<WF>(fplane, col.z, col.y, ha, ia, wfa, wca);
         const float wA = (ia == va) ? wfa : ((ia + 1 == va) ? wca : 0.0f);
         if (wA == 0.0f) continue;
-        // v of the column's rays on this plane: (A + B z) / W
+        // v of the column's rays on this plane: (A + P6 z) / W, affine in z
         const float pa = __builtin_fmaf(fplane, col.z, col.y);
         const float qx = (m == 0) ? fx : pa, qy = (m == 0) ? pa : fy;
         const float A = __builtin_fmaf(P[4], qx, __builtin_fmaf(P[5], qy, P[7]));
         const float W = __builtin_fmaf(P[8], qx, __builtin_fmaf(P[9], qy, P[11]));
+        const float4* R = RY + (size_t)iu * pitch;
+        float s0 = 0.0f, s1 = 0.0f;
+        int nc = 0;  // wave-uniform bound on the candidates per lane
         int iv_lo = 0, iv_hi = n_v - 1;
         if (W > 1.0e-6f) {
           // rays whose axis-2 coordinate lies in [z - 1, z + 2) reach the pair
           const float inv = 1.0f / W;
-          const float v0 = (A + P[6] * (fz - 1.0f - e)) * inv;
-          const float v1 = (A + P[6] * (fz + 2.0f + e)) * inv;
-          iv_lo = max(0, (int)ceilf(fmaxf(fminf(v0, v1) - margin, -1.0f)));
-          iv_hi = min(n_v - 1, (int)floorf(fminf(fmaxf(v0, v1) + margin, (float)n_v)));
+          const float slope = P[6] * inv;                // pixels per voxel along z
+          const float base = A * inv;
+          const float va0 = __builtin_fmaf(slope, fz - 1.0f - e, base);
+          const float va1 = __builtin_fmaf(slope, fz + 2.0f + e, base);
+          const float lo = fminf(va0, va1) - margin, hi = fmaxf(va0, va1) + margin;
+          iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
+          iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
+          // an interval of length L holds at most floor(L) + 1 integers
+          nc = (int)(fabsf(slope) * (3.0f + 2.0f * e) + 2.0f * margin + 1.0e-3f) + 1;
+          if (!zin) iv_lo = n_v;   // reads the column's empty entries only
         }
-        if (!zin) iv_hi = iv_lo - 1;
-        const float4* R = RY + (size_t)iu * n_v;
-        // the first NC candidates are loaded together (indices clamped into
-        // the column), then consumed; wider ranges fall through to a loop
-        float4 rr[NC];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) rr[k] = R[min(iv_lo + k, n_v - 1)];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          const float4 r = rr[k];
-          const uint32_t mr = __float_as_uint(r.x);
-          const int i0 = (int)((mr >> 2) & 0x7fffu);
-          const int i1 = (int)(mr >> 17);
-          int ib;
-          float wfb, wcb;
-          sample_axis<WF>(fplane, r.z, r.y, hz, ib, wfb, wcb);
-          const int d = ib - z;  // the sample's floor relative to the pair
-          float b0 = (d == 0) ? wfb : ((d == -1) ? wcb : 0.0f);
-          float b1 = (d == 1) ? wfb : ((d == 0) ? wcb : 0.0f);
-          const bool ok = (iv_lo + k <= iv_hi) && plane >= i0 && plane < i1;
-          const float wa = ok ? r.w * wA : 0.0f;
-          acc0 = __builtin_fmaf(wa, b0, acc0);
-          acc1 = __builtin_fmaf(wa, b1, acc1);
+        switch (nc) {
+          case 1:
+          case 2: pair_candidates<WF, 2>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+          case 3: pair_candidates<WF, 3>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+          case 4: pair_candidates<WF, 4>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+          case 5: pair_candidates<WF, 5>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+          case 6: pair_candidates<WF, 6>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+          case 7: pair_candidates<WF, 7>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+          case 8: pair_candidates<WF, 8>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+          default:
+            // long or unbounded candidate ranges: explicit per-lane loop
+            if (!zin) iv_hi = iv_lo - 1;
+            for (int iv = iv_lo; iv <= iv_hi; ++iv) {
+              const float4 r = R[iv];
+              const uint32_t mr = __float_as_uint(r.x);
+              const int i0 = (int)((mr >> 2) & 0x7fffu);
+              const int i1 = (int)(mr >> 17);
+              if (plane < i0 || plane >= i1) continue;
+              float b0, b1;
+              pair_weights<WF>(fplane, r.z, r.y, hz, fz, z, b0, b1);
+              s0 = __builtin_fmaf(r.w, b0, s0);
+              s1 = __builtin_fmaf(r.w, b1, s1);
+            }
+            break;
         }
-        for (int iv = iv_lo + NC; iv <= iv_hi; ++iv) {
-          const float4 r = R[iv];
-          const uint32_t mr = __float_as_uint(r.x);
-          const int i0 = (int)((mr >> 2) & 0x7fffu);
-          const int i1 = (int)(mr >> 17);
-          if (plane < i0 || plane >= i1) continue;
-          int ib;
-          float wfb, wcb;
-          sample_axis<WF>(fplane, r.z, r.y, hz, ib, wfb, wcb);
-          const int d = ib - z;
-          const float b0 = (d == 0) ? wfb : ((d == -1) ? wcb : 0.0f);
-          const float b1 = (d == 1) ? wfb : ((d == 0) ? wcb : 0.0f);
-          const float wa = r.w * wA;
-          acc0 = __builtin_fmaf(wa, b0, acc0);
-          acc1 = __builtin_fmaf(wa, b1, acc1);
-        }
+        acc0 = __builtin_fmaf(wA, s0, acc0);
+        acc1 = __builtin_fmaf(wA, s1, acc1);
       }
     }
   }
@@ -742,24 +868,24 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
 __global__ __launch_bounds__(256) void batched_pad_kernel(const BatchInst* __restrict__ insts) {
   const BatchInst& I = insts[blockIdx.y];
   const int n0 = I.a.G.n[0], n1 = I.a.G.n[1], n2 = I.a.G.n[2];
-  const long long p2 = n2 + 2, p1 = n1 + 2;
+  const long long p2 = padded_pitch(n2), p1 = n1 + 2;
   const long long total = I.padded_elems;
-  const bool two = (I.dtype != 0);
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total;
        e += (long long)gridDim.x * 256) {
-    const long long z = e % p2;
+    const int z = (int)(e % p2);
     const long long t = e / p2;
-    const long long y = t % p1;
-    const long long x = t / p1;
-    const bool in = x >= 1 && x <= n0 && y >= 1 && y <= n1 && z >= 1 && z <= n2;
-    const long long src = ((x - 1) * n1 + (y - 1)) * (long long)n2 + (z - 1);
-    if (two) {
-      const uint16_t* s = static_cast<const uint16_t*>(I.src);
-      static_cast<uint16_t*>(I.padded)[e] = in ? s[src] : (uint16_t)0;
-    } else {
-      const uint32_t* s = static_cast<const uint32_t*>(I.src);
-      static_cast<uint32_t*>(I.padded)[e] = in ? s[src] : 0u;
-    }
+    const int y = (int)(t % p1);
+    const int x = (int)(t / p1);
+    if (I.dtype != 0)
+      pad_pair_element(static_cast<const uint16_t*>(I.src),
+                       static_cast<uint16_t*>(const_cast<void*>(I.a.vol_a)),
+                       static_cast<uint16_t*>(const_cast<void*>(I.a.vol_b)), n0, n1, n2, e, x,
+                       y, z);
+    else
+      pad_pair_element(static_cast<const uint32_t*>(I.src),
+                       static_cast<uint32_t*>(const_cast<void*>(I.a.vol_a)),
+                       static_cast<uint32_t*>(const_cast<void*>(I.a.vol_b)), n0, n1, n2, e, x,
+                       y, z);
   }
 }
 
@@ -820,15 +946,18 @@ static int check_launch(const char* what) {
 
 size_t dtype_size(int dtype) { return dtype == 0 ? 4 : 2; }
 
-int launch_pad(const void* src, void* dst, int dtype, const int n[3], hipStream_t s) {
-  dim3 grid((unsigned)((n[2] + 2 + 255) / 256), (unsigned)(n[1] + 2), (unsigned)(n[0] + 2));
+int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int n[3],
+               hipStream_t s) {
+  dim3 grid((unsigned)((padded_pitch(n[2]) + 255) / 256), (unsigned)(n[1] + 2), (unsigned)(n[0] + 2));
   TimedLaunch t = timing_begin("pad", s);
   if (dtype == 0)
     pad_kernel<uint32_t><<<grid, 256, 0, s>>>(static_cast<const uint32_t*>(src),
-                                               static_cast<uint32_t*>(dst), n[0], n[1], n[2]);
+                                               static_cast<uint32_t*>(copy_a),
+                                               static_cast<uint32_t*>(copy_b), n[0], n[1], n[2]);
   else
     pad_kernel<uint16_t><<<grid, 256, 0, s>>>(static_cast<const uint16_t*>(src),
-                                               static_cast<uint16_t*>(dst), n[0], n[1], n[2]);
+                                               static_cast<uint16_t*>(copy_a),
+                                               static_cast<uint16_t*>(copy_b), n[0], n[1], n[2]);
   timing_end("pad", t, s);
   return check_launch("pad kernel");
 }
@@ -880,8 +1009,11 @@ int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4
   TimedLaunch t = timing_begin("adjoint_gather", s);
   const int acc = accumulate ? 1 : 0;
   if (g->separable) {
-    dim3 grid((unsigned)((g->n[2] + 127) / 128), (unsigned)((g->n[1] + 3) / 4),
-              (unsigned)g->n[0]);
+    int nzb, nyb, ntx, nty;
+    gather_grid(g->gg.n, nzb, nyb, ntx, nty);
+    const unsigned long long nwg = (unsigned long long)ntx * GTX * nty * GTY * nzb;
+    if (nwg > 0x7fffffffull) return set_error(-4, "adjoint: volume too large for one launch");
+    const unsigned grid = (unsigned)nwg;
     if (g->weight == W_SPLINE)
       adj_gather_sep_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table,
                                                            cols, mask, view0, c0, n_chunk, acc,

@@ -32,6 +32,11 @@ struct GridGeom {
   int beam;
 };
 
+// Row pitch (elements) of the zero-padded volume copy: n2 + 2 rounded up to
+// an even count, so that every row starts on a 4-byte boundary for 16-bit
+// storage. The extra column holds zeros and is never sampled.
+GJP_HD long long padded_pitch(int n2) { return (long long)((n2 + 3) & ~1); }
+
 // Result of the per-ray setup.
 struct RaySetup {
   int m;            // driving axis (Eq. 3)
@@ -44,9 +49,12 @@ struct RaySetup {
 
 // Sample predicate on one transverse axis: the coordinate of plane i on the
 // line s + (i - s_m) g (Eq. 6 with o = -s_m) lies in the zero-padded domain.
-GJP_HD bool inside_axis(double s_k, double neg_sm, double g_k, int i, int n_k) {
-  const double p = s_k + (neg_sm + (double)i) * g_k;
+GJP_HD bool inside_axis(double s_k, double neg_sm, double g_k, double di, int n_k) {
+  const double p = s_k + (neg_sm + di) * g_k;
   return p > -1.0 && p < (double)n_k;
+}
+GJP_HD bool inside_axis(double s_k, double neg_sm, double g_k, int i, int n_k) {
+  return inside_axis(s_k, neg_sm, g_k, (double)i, n_k);
 }
 
 GJP_HD bool inside_both(const double* s, double neg_sm, const double* g, int a, int b,
@@ -129,11 +137,34 @@ GJP_HD void ray_setup(const double* __restrict__ v, const GridGeom& G, int iu, i
   i0 = i0 < 0 ? 0 : (i0 > nm ? nm : i0);
   i1 = i1 < 0 ? 0 : (i1 > nm ? nm : i1);
   if (i1 < i0) i1 = i0;
-  while (i0 < i1 && !inside_both(s, neg_sm, g, a, b, G.n, i0)) ++i0;
-  while (i0 > 0 && inside_both(s, neg_sm, g, a, b, G.n, i0 - 1)) --i0;
+  // inside_both's predicate on the plane index held as an exact double next
+  // to the integer (same arithmetic; keeps the device register count low)
+  const double sa = s[a], sb = s[b], ga = g[a], gb = g[b];
+  const int na = G.n[a], nb = G.n[b];
+  auto inside = [=](double di) {
+    return inside_axis(sa, neg_sm, ga, di, na) && inside_axis(sb, neg_sm, gb, di, nb);
+  };
+  double d0 = (double)i0;
+  while (i0 < i1 && !inside(d0)) {
+    ++i0;
+    d0 += 1.0;
+  }
+  d0 = (double)(i0 - 1);
+  while (i0 > 0 && inside(d0)) {
+    --i0;
+    d0 -= 1.0;
+  }
   if (i1 < i0) i1 = i0;
-  while (i1 > i0 && !inside_both(s, neg_sm, g, a, b, G.n, i1 - 1)) --i1;
-  while (i1 < nm && inside_both(s, neg_sm, g, a, b, G.n, i1)) ++i1;
+  double d1 = (double)(i1 - 1);
+  while (i1 > i0 && !inside(d1)) {
+    --i1;
+    d1 -= 1.0;
+  }
+  d1 = (double)i1;
+  while (i1 < nm && inside(d1)) {
+    ++i1;
+    d1 += 1.0;
+  }
   R.i0 = i0;
   R.i1 = i1;
 }
