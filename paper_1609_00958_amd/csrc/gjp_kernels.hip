@@ -723,21 +723,26 @@ __device__ __forceinline__ void pair_candidates(const float4* __restrict__ R, in
   }
 }
 
-// Workgroup placement of the gather: a workgroup covers 4 rows (x, y .. y+3)
-// of 128 voxels along axis 2. Logical workgroup indices are ordered in tiles
-// of GTX x-planes by GTY row blocks (axis-2 blocks fastest), and each XCD
-// walks one contiguous range of them, so the workgroups resident on an XCD
-// cover a compact (x, y) region whose rays come from a few detector columns
-// per view: the ray table they read stays in that XCD's L2.
-constexpr int GTX = 16, GTY = 8;
+// Workgroup placement of the gather: a lane owns a 2 x 2 x 2 voxel block
+// (x, x+1) x (y, y+1) x (z, z+1); a wavefront covers 128 voxels along axis 2
+// and a workgroup four such wavefronts along y (8 rows). Logical workgroup
+// indices are ordered in tiles of GTX x-pairs by GTY row blocks (axis-2 blocks
+// fastest), and each XCD walks one contiguous range of them, so the
+// workgroups resident on an XCD cover a compact (x, y) region whose rays come
+// from a few detector columns per view: the ray table they read stays in that
+// XCD's L2.
+constexpr int GTX = 8, GTY = 4;
 
 __host__ __device__ inline void gather_grid(const int* n, int& nzb, int& nyb, int& ntx, int& nty) {
   nzb = (n[2] + 127) / 128;
-  nyb = (n[1] + 3) / 4;
-  ntx = (n[0] + GTX - 1) / GTX;
+  nyb = (n[1] + 7) / 8;
+  ntx = ((n[0] + 1) / 2 + GTX - 1) / GTX;
   nty = (nyb + GTY - 1) / GTY;
 }
 
+// The two planes of a lane's block along the driving axis m, each with the
+// two in-plane rows: one candidate list per column serves both rows (the
+// column's in-plane weight differs per row, the axis-2 weights do not).
 template <int WF>
 __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
     const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
@@ -752,21 +757,22 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
   const int w = (int)(L - (uint32_t)tile * per_tile);
   const int zb = w % nzb;
   const int iyb = (w / nzb) % GTY;
-  const int ix = w / (nzb * GTY);
-  const int x = (tile / nty) * GTX + ix;
+  const int ixp = w / (nzb * GTY);
+  const int x = 2 * ((tile / nty) * GTX + ixp);
   const int yb = (tile % nty) * GTY + iyb;
   if (x >= G.n[0] || yb >= nyb) return;
-  // a lane owns the voxel pair (x, y, z) and (x, y, z + 1)
-  const int z = 2 * (zb * 64 + (int)(threadIdx.x & 63));
-  const int y = yb * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int y = yb * 8 + 2 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (y >= G.n[1]) return;
+  const int z = 2 * (zb * 64 + (int)(threadIdx.x & 63));
   const bool zin = z < G.n[2];
-  const float fx = (float)x, fy = (float)y, fz = (float)z;
-  const float hx = G.hi[0], hy = G.hi[1], hz = G.hi[2];
+  const float fz = (float)z;
+  const float hz = G.hi[2];
   const float e = 0.002f;       // widened neighbourhood (voxels)
   const float margin = 0.05f;   // widened ranges (pixels)
   const int pitch = n_v + kColumnPad;  // table entries per detector column
-  float acc0 = 0.0f, acc1 = 0.0f;
+  // acc_XYZ: voxel (x + X, y + Y, z + Z)
+  float acc000 = 0.0f, acc001 = 0.0f, acc010 = 0.0f, acc011 = 0.0f;
+  float acc100 = 0.0f, acc101 = 0.0f, acc110 = 0.0f, acc111 = 0.0f;
   for (int c = c0; c < c0 + n_chunk; ++c) {
     const int mk = mask[c];
     if (!mk) continue;
@@ -775,89 +781,126 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
     const float4* RY = rays + (size_t)c * n_u * pitch;
     for (int m = 0; m < 2; ++m) {
       if (!(mk & (1 << m))) continue;
-      const int plane = (m == 0) ? x : y;
-      const float fplane = (m == 0) ? fx : fy;
-      const int va = (m == 0) ? y : x;
-      const float ha = (m == 0) ? hy : hx;
-      // candidate columns: u of (plane, va -+ (1 + e)); u does not depend on z here
-      const float ea = 1.0f + e;
-      const float qx0 = (m == 0) ? fx : fx - ea, qy0 = (m == 0) ? fy - ea : fy;
-      const float qx1 = (m == 0) ? fx : fx + ea, qy1 = (m == 0) ? fy + ea : fy;
-      const float un0 = __builtin_fmaf(P[0], qx0, __builtin_fmaf(P[1], qy0, P[3]));
-      const float w0 = __builtin_fmaf(P[8], qx0, __builtin_fmaf(P[9], qy0, P[11]));
-      const float un1 = __builtin_fmaf(P[0], qx1, __builtin_fmaf(P[1], qy1, P[3]));
-      const float w1 = __builtin_fmaf(P[8], qx1, __builtin_fmaf(P[9], qy1, P[11]));
-      int iu_lo = 0, iu_hi = n_u - 1;
-      if (w0 > 1.0e-6f && w1 > 1.0e-6f) {
-        const float u0 = un0 / w0, u1 = un1 / w1;
-        iu_lo = max(0, (int)ceilf(fmaxf(fminf(u0, u1) - margin, -1.0f)));
-        iu_hi = min(n_u - 1, (int)floorf(fminf(fmaxf(u0, u1) + margin, (float)n_u)));
-      }
-      for (int iu = iu_lo; iu <= iu_hi; ++iu) {
-        const float4 col = C[iu];
-        if ((int)__float_as_uint(col.x) != m) continue;
-        int ia;
-        float wfa, wca;
-        sample_axis<WF>(fplane, col.z, col.y, ha, ia, wfa, wca);
-        const float wA = (ia == va) ? wfa : ((ia + 1 == va) ? wca : 0.0f);
-        if (wA == 0.0f) continue;
-        // v of the column's rays on this plane: (A + P6 z) / W, affine in z
-        const float pa = __builtin_fmaf(fplane, col.z, col.y);
-        const float qx = (m == 0) ? fx : pa, qy = (m == 0) ? pa : fy;
-        const float A = __builtin_fmaf(P[4], qx, __builtin_fmaf(P[5], qy, P[7]));
-        const float W = __builtin_fmaf(P[8], qx, __builtin_fmaf(P[9], qy, P[11]));
-        const float4* R = RY + (size_t)iu * pitch;
-        float s0 = 0.0f, s1 = 0.0f;
-        int nc = 0;  // wave-uniform bound on the candidates per lane
-        int iv_lo = 0, iv_hi = n_v - 1;
-        if (W > 1.0e-6f) {
-          // rays whose axis-2 coordinate lies in [z - 1, z + 2) reach the pair
-          const float inv = 1.0f / W;
-          const float slope = P[6] * inv;                // pixels per voxel along z
-          const float base = A * inv;
-          const float va0 = __builtin_fmaf(slope, fz - 1.0f - e, base);
-          const float va1 = __builtin_fmaf(slope, fz + 2.0f + e, base);
-          const float lo = fminf(va0, va1) - margin, hi = fmaxf(va0, va1) + margin;
-          iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
-          iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
-          // an interval of length L holds at most floor(L) + 1 integers
-          nc = (int)(fabsf(slope) * (3.0f + 2.0f * e) + 2.0f * margin + 1.0e-3f) + 1;
-          if (!zin) iv_lo = n_v;   // reads the column's empty entries only
+      const int va = (m == 0) ? y : x;  // first of the two in-plane rows
+      const float fva = (float)va;
+      const float ha = (m == 0) ? G.hi[1] : G.hi[0];
+      for (int dp = 0; dp < 2; ++dp) {
+        const int plane = ((m == 0) ? x : y) + dp;
+        if (plane >= G.n[m]) continue;
+        const float fplane = (float)plane;
+        // candidate columns: u of (plane, va - (1 + e)) and (plane, va + 1 + (1 + e))
+        const float qa0 = fva - 1.0f - e, qa1 = fva + 2.0f + e;
+        const float qx0 = (m == 0) ? fplane : qa0, qy0 = (m == 0) ? qa0 : fplane;
+        const float qx1 = (m == 0) ? fplane : qa1, qy1 = (m == 0) ? qa1 : fplane;
+        const float un0 = __builtin_fmaf(P[0], qx0, __builtin_fmaf(P[1], qy0, P[3]));
+        const float w0 = __builtin_fmaf(P[8], qx0, __builtin_fmaf(P[9], qy0, P[11]));
+        const float un1 = __builtin_fmaf(P[0], qx1, __builtin_fmaf(P[1], qy1, P[3]));
+        const float w1 = __builtin_fmaf(P[8], qx1, __builtin_fmaf(P[9], qy1, P[11]));
+        int iu_lo = 0, iu_hi = n_u - 1;
+        if (w0 > 1.0e-6f && w1 > 1.0e-6f) {
+          const float u0 = un0 * __builtin_amdgcn_rcpf(w0), u1 = un1 * __builtin_amdgcn_rcpf(w1);
+          iu_lo = max(0, (int)ceilf(fmaxf(fminf(u0, u1) - margin, -1.0f)));
+          iu_hi = min(n_u - 1, (int)floorf(fminf(fmaxf(u0, u1) + margin, (float)n_u)));
         }
-        switch (nc) {
-          case 1:
-          case 2: pair_candidates<WF, 2>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-          case 3: pair_candidates<WF, 3>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-          case 4: pair_candidates<WF, 4>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-          case 5: pair_candidates<WF, 5>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-          case 6: pair_candidates<WF, 6>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-          case 7: pair_candidates<WF, 7>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-          case 8: pair_candidates<WF, 8>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-          default:
-            // long or unbounded candidate ranges: explicit per-lane loop
-            if (!zin) iv_hi = iv_lo - 1;
-            for (int iv = iv_lo; iv <= iv_hi; ++iv) {
-              const float4 r = R[iv];
-              const uint32_t mr = __float_as_uint(r.x);
-              const int i0 = (int)((mr >> 2) & 0x7fffu);
-              const int i1 = (int)(mr >> 17);
-              if (plane < i0 || plane >= i1) continue;
-              float b0, b1;
-              pair_weights<WF>(fplane, r.z, r.y, hz, fz, z, b0, b1);
-              s0 = __builtin_fmaf(r.w, b0, s0);
-              s1 = __builtin_fmaf(r.w, b1, s1);
+        for (int iu = iu_lo; iu <= iu_hi; ++iu) {
+          const float4 col = C[iu];
+          if ((int)__float_as_uint(col.x) != m) continue;
+          int ia;
+          float wfa, wca;
+          sample_axis<WF>(fplane, col.z, col.y, ha, ia, wfa, wca);
+          const float wA0 = (ia == va) ? wfa : ((ia + 1 == va) ? wca : 0.0f);
+          const float wA1 = (ia == va + 1) ? wfa : ((ia == va) ? wca : 0.0f);
+          if (wA0 == 0.0f && wA1 == 0.0f) continue;
+          // v of the column's rays on this plane: (A + P6 z) / W, affine in z
+          const float pa = __builtin_fmaf(fplane, col.z, col.y);
+          const float qx = (m == 0) ? fplane : pa, qy = (m == 0) ? pa : fplane;
+          const float A = __builtin_fmaf(P[4], qx, __builtin_fmaf(P[5], qy, P[7]));
+          const float W = __builtin_fmaf(P[8], qx, __builtin_fmaf(P[9], qy, P[11]));
+          const float4* R = RY + (size_t)iu * pitch;
+          float s0 = 0.0f, s1 = 0.0f;
+          int nc = 0;  // wave-uniform bound on the candidates per lane
+          int iv_lo = 0, iv_hi = n_v - 1;
+          if (W > 1.0e-6f) {
+            // rays whose axis-2 coordinate lies in [z - 1, z + 2) reach the pair
+            const float inv = __builtin_amdgcn_rcpf(W);
+            const float slope = P[6] * inv;  // pixels per voxel along z
+            const float base = A * inv;
+            const float va0 = __builtin_fmaf(slope, fz - 1.0f - e, base);
+            const float va1 = __builtin_fmaf(slope, fz + 2.0f + e, base);
+            const float lo = fminf(va0, va1) - margin, hi = fmaxf(va0, va1) + margin;
+            iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
+            iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
+            // an interval of length L holds at most floor(L) + 1 integers
+            nc = (int)(fabsf(slope) * (3.0f + 2.0f * e) + 2.0f * margin + 1.0e-3f) + 1;
+            if (!zin) iv_lo = n_v;  // reads the column's empty entries only
+          }
+          switch (nc) {
+            case 1:
+            case 2: pair_candidates<WF, 2>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+            case 3: pair_candidates<WF, 3>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+            case 4: pair_candidates<WF, 4>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+            case 5: pair_candidates<WF, 5>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+            case 6: pair_candidates<WF, 6>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+            case 7: pair_candidates<WF, 7>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+            case 8: pair_candidates<WF, 8>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
+            default:
+              // long or unbounded candidate ranges: explicit per-lane loop
+              if (!zin) iv_hi = iv_lo - 1;
+              for (int iv = iv_lo; iv <= iv_hi; ++iv) {
+                const float4 r = R[iv];
+                const uint32_t mr = __float_as_uint(r.x);
+                const int i0 = (int)((mr >> 2) & 0x7fffu);
+                const int i1 = (int)(mr >> 17);
+                if (plane < i0 || plane >= i1) continue;
+                float b0, b1;
+                pair_weights<WF>(fplane, r.z, r.y, hz, fz, z, b0, b1);
+                s0 = __builtin_fmaf(r.w, b0, s0);
+                s1 = __builtin_fmaf(r.w, b1, s1);
+              }
+              break;
+          }
+          // plane index dp and row index (0: va, 1: va + 1) of the block
+          if (m == 0) {
+            if (dp == 0) {
+              acc000 = __builtin_fmaf(wA0, s0, acc000); acc001 = __builtin_fmaf(wA0, s1, acc001);
+              acc010 = __builtin_fmaf(wA1, s0, acc010); acc011 = __builtin_fmaf(wA1, s1, acc011);
+            } else {
+              acc100 = __builtin_fmaf(wA0, s0, acc100); acc101 = __builtin_fmaf(wA0, s1, acc101);
+              acc110 = __builtin_fmaf(wA1, s0, acc110); acc111 = __builtin_fmaf(wA1, s1, acc111);
             }
-            break;
+          } else {
+            if (dp == 0) {
+              acc000 = __builtin_fmaf(wA0, s0, acc000); acc001 = __builtin_fmaf(wA0, s1, acc001);
+              acc100 = __builtin_fmaf(wA1, s0, acc100); acc101 = __builtin_fmaf(wA1, s1, acc101);
+            } else {
+              acc010 = __builtin_fmaf(wA0, s0, acc010); acc011 = __builtin_fmaf(wA0, s1, acc011);
+              acc110 = __builtin_fmaf(wA1, s0, acc110); acc111 = __builtin_fmaf(wA1, s1, acc111);
+            }
+          }
         }
-        acc0 = __builtin_fmaf(wA, s0, acc0);
-        acc1 = __builtin_fmaf(wA, s1, acc1);
       }
     }
   }
-  if (zin) {
-    float* out = vol + ((size_t)x * G.n[1] + y) * G.n[2] + z;
-    out[0] = accumulate ? (out[0] + acc0) : acc0;
-    if (z + 1 < G.n[2]) out[1] = accumulate ? (out[1] + acc1) : acc1;
+  if (!zin) return;
+  const bool z1 = z + 1 < G.n[2];
+  const bool y1 = y + 1 < G.n[1];
+  const bool x1 = x + 1 < G.n[0];
+  const size_t sx = (size_t)G.n[1] * G.n[2], sy = (size_t)G.n[2];
+  float* o = vol + (size_t)x * sx + (size_t)y * sy + z;
+  auto put = [&](float* q, float v) { *q = accumulate ? (*q + v) : v; };
+  put(o, acc000);
+  if (z1) put(o + 1, acc001);
+  if (y1) {
+    put(o + sy, acc010);
+    if (z1) put(o + sy + 1, acc011);
+  }
+  if (x1) {
+    put(o + sx, acc100);
+    if (z1) put(o + sx + 1, acc101);
+    if (y1) {
+      put(o + sx + sy, acc110);
+      if (z1) put(o + sx + sy + 1, acc111);
+    }
   }
 }
 
