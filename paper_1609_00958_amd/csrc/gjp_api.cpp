@@ -524,6 +524,8 @@ void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* pad
   a.n_v = g->n_v;
   a.tile_v_log2 = tile.tile_v_log2;
   a.remap = tile.remap;
+  a.view_group = tile.view_group < 1 ? 1 : tile.view_group;
+  a.n_views = g->n_views;
   const int tile_v = 1 << tile.tile_v_log2;
   const int tile_u = 256 >> tile.tile_v_log2;
   a.tiles_v = (g->n_v + tile_v - 1) / tile_v;
@@ -618,10 +620,10 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
   FwdTile best;
   float best_ms = 3.0e38f;
   for (int k : {6, 5, 4}) {
-    for (int remap : {1, 0}) {
+    for (int vg : {8, 16, 1}) {
       FwdTile t;
       t.tile_v_log2 = k;
-      t.remap = remap;
+      t.view_group = vg;
       st = forward_with_tile(g, d_vol, vol_dtype, d_sino, s, t);  // warm-up
       if (st != GJP_OK) break;
       GJP_HIP(hipEventRecord(e0, s), "autotune record");
@@ -840,11 +842,17 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
   } catch (...) {
     return fail(GJP_ENOMEM, "batched: work list");
   }
+  // within an instance: groups of view_group views, each tile for all views
+  // of the group in turn (the single-instance launch order, for L2 reuse)
   for (const auto& oc : order) {
     const BatchInst& I = P->host[oc.inst];
-    for (int v = 0; v < I.n_views; ++v)
+    const int K = std::max(1, I.a.view_group);
+    for (int v0 = 0; v0 < I.n_views; v0 += K) {
+      const int kg = std::min(K, I.n_views - v0);
       for (int t = 0; t < I.a.tiles_per_view; ++t)
-        items.push_back(make_uint2((uint32_t)oc.inst | ((uint32_t)v << 12), (uint32_t)t));
+        for (int v = v0; v < v0 + kg; ++v)
+          items.push_back(make_uint2((uint32_t)oc.inst | ((uint32_t)v << 12), (uint32_t)t));
+    }
   }
   P->n_items = (int)items.size();
   GJP_HIP(hipMalloc(&P->d_items, std::max<size_t>(1, items.size()) * sizeof(uint2)),

@@ -59,6 +59,7 @@ constexpr int kColumnPad = 8;
 struct FwdTile {
   int tile_v_log2 = 6;  // detector pixels along v per wavefront row (64, 32, 16)
   int remap = 1;        // 1: contiguous tile ranges per XCD
+  int view_group = 8;   // consecutive views that share each tile's turn
 };
 
 // Arguments of one forward launch (one volume, a range of views).
@@ -72,6 +73,8 @@ struct FwdArgs {
   long long S0, S1;     // padded strides in pair elements
   int n_u, n_v;
   int tile_v_log2;
+  int view_group;       // views interleaved per tile in the launch order
+  int n_views;          // views of this launch
   int tiles_v, tiles_u, tiles_per_view;
   int remap;
 };

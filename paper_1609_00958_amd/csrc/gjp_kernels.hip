@@ -413,13 +413,21 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
   fwd_ray<T, WF, IDX64>(a, view, valid ? iu : 0, valid ? iv : 0, valid);
 }
 
+// Launch order: groups of view_group consecutive views; within a group each
+// tile comes up for all the group's views in turn. Rays of nearby views cross
+// nearly the same voxels, so the workgroups resident on an XCD share their
+// volume reads in L2 instead of each view streaming the volume again.
 template <typename T, int WF, bool IDX64>
 __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
   uint32_t b = blockIdx.x;
   if (a.remap) b = xcd_remap(b, gridDim.x);
-  const int view = (int)(b / (uint32_t)a.tiles_per_view);
-  const int t = (int)(b - (uint32_t)view * (uint32_t)a.tiles_per_view);
-  fwd_tile<T, WF, IDX64>(a, view, t);
+  const uint32_t K = (uint32_t)a.view_group, tpv = (uint32_t)a.tiles_per_view;
+  const uint32_t grp = b / (K * tpv);
+  const uint32_t r = b - grp * K * tpv;
+  const uint32_t v0 = grp * K;
+  const uint32_t kg = min(K, (uint32_t)a.n_views - v0);  // views in this group
+  const uint32_t t = r / kg;
+  fwd_tile<T, WF, IDX64>(a, (int)(v0 + (r - t * kg)), (int)t);
 }
 
 // ---------------------------------------------------------------------------
