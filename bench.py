@@ -159,7 +159,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--autotune", action="store_true", help="autotune the forward tile first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the forward autotuning that precedes the warm-up (untimed)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy before the steps (untimed), a "
                          "reference kernel of known traffic for hardware byte counters")
@@ -196,7 +197,7 @@ def main():
     x_f16 = x.to(torch.float16)
     xr = x.clone().requires_grad_(True)
     w = torch.rand(G.sino_shape, generator=torch.Generator().manual_seed(3)).to(dev)
-    if args.autotune:
+    if not args.no_autotune:
         for v in (x, x_bf16, x_f16):
             log(f"autotune {v.dtype}: tile_v = {gjp.autotune(v, G)}")
     torch.cuda.synchronize()

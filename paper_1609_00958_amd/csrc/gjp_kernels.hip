@@ -709,11 +709,13 @@ __device__ __forceinline__ void pair_weights(float fplane, float g, float c, flo
   }
 }
 
-// NC candidate rays R[iv_lo .. iv_lo + NC): all loads first, then the sums.
+// NC candidate rays R[iv_lo .. iv_lo + NC), each loaded once and evaluated on
+// the two planes p0 and p0 + 1 for the voxel pair (z, z + 1): sums s<plane><z>.
 template <int WF, int NC>
-__device__ __forceinline__ void pair_candidates(const float4* __restrict__ R, int iv_lo, int plane,
-                                                float fplane, float hz, float fz, int z,
-                                                float& c0, float& c1) {
+__device__ __forceinline__ void block_candidates(const float4* __restrict__ R, int iv_lo, int p0,
+                                                 float fp0, float hz, float fz, int z,
+                                                 float& s00, float& s01, float& s10,
+                                                 float& s11) {
   float4 rr[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) rr[k] = R[iv_lo + k];
@@ -724,10 +726,14 @@ __device__ __forceinline__ void pair_candidates(const float4* __restrict__ R, in
     const int i0 = (int)((mr >> 2) & 0x7fffu);
     const int i1 = (int)(mr >> 17);
     float b0, b1;
-    pair_weights<WF>(fplane, r.z, r.y, hz, fz, z, b0, b1);
-    const float wy = (plane >= i0 && plane < i1) ? r.w : 0.0f;
-    c0 = __builtin_fmaf(wy, b0, c0);
-    c1 = __builtin_fmaf(wy, b1, c1);
+    pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, b0, b1);
+    const float wy0 = (p0 >= i0 && p0 < i1) ? r.w : 0.0f;
+    s00 = __builtin_fmaf(wy0, b0, s00);
+    s01 = __builtin_fmaf(wy0, b1, s01);
+    pair_weights<WF>(fp0 + 1.0f, r.z, r.y, hz, fz, z, b0, b1);
+    const float wy1 = (p0 + 1 >= i0 && p0 + 1 < i1) ? r.w : 0.0f;
+    s10 = __builtin_fmaf(wy1, b0, s10);
+    s11 = __builtin_fmaf(wy1, b1, s11);
   }
 }
 
@@ -792,99 +798,128 @@ __global__ __launch_bounds__(256) void adj_gather_sep_kernel(
       const int va = (m == 0) ? y : x;  // first of the two in-plane rows
       const float fva = (float)va;
       const float ha = (m == 0) ? G.hi[1] : G.hi[0];
+      const int p0 = (m == 0) ? x : y;  // first of the two planes
+      const float fp0 = (float)p0, fp1 = fp0 + 1.0f;
+      const bool two = p0 + 1 < G.n[m];
+      // candidate columns: u of (plane, va - (1 + e)) and (plane, va + 1 + (1 + e))
+      // on both planes
+      const float qa0 = fva - 1.0f - e, qa1 = fva + 2.0f + e;
+      int iu_lo = n_u, iu_hi = -1;
+      bool iu_all = false;
       for (int dp = 0; dp < 2; ++dp) {
-        const int plane = ((m == 0) ? x : y) + dp;
-        if (plane >= G.n[m]) continue;
-        const float fplane = (float)plane;
-        // candidate columns: u of (plane, va - (1 + e)) and (plane, va + 1 + (1 + e))
-        const float qa0 = fva - 1.0f - e, qa1 = fva + 2.0f + e;
-        const float qx0 = (m == 0) ? fplane : qa0, qy0 = (m == 0) ? qa0 : fplane;
-        const float qx1 = (m == 0) ? fplane : qa1, qy1 = (m == 0) ? qa1 : fplane;
+        const float fpl = dp ? fp1 : fp0;
+        const float qx0 = (m == 0) ? fpl : qa0, qy0 = (m == 0) ? qa0 : fpl;
+        const float qx1 = (m == 0) ? fpl : qa1, qy1 = (m == 0) ? qa1 : fpl;
         const float un0 = __builtin_fmaf(P[0], qx0, __builtin_fmaf(P[1], qy0, P[3]));
         const float w0 = __builtin_fmaf(P[8], qx0, __builtin_fmaf(P[9], qy0, P[11]));
         const float un1 = __builtin_fmaf(P[0], qx1, __builtin_fmaf(P[1], qy1, P[3]));
         const float w1 = __builtin_fmaf(P[8], qx1, __builtin_fmaf(P[9], qy1, P[11]));
-        int iu_lo = 0, iu_hi = n_u - 1;
         if (w0 > 1.0e-6f && w1 > 1.0e-6f) {
           const float u0 = un0 * __builtin_amdgcn_rcpf(w0), u1 = un1 * __builtin_amdgcn_rcpf(w1);
-          iu_lo = max(0, (int)ceilf(fmaxf(fminf(u0, u1) - margin, -1.0f)));
-          iu_hi = min(n_u - 1, (int)floorf(fminf(fmaxf(u0, u1) + margin, (float)n_u)));
+          iu_lo = min(iu_lo, max(0, (int)ceilf(fmaxf(fminf(u0, u1) - margin, -1.0f))));
+          iu_hi = max(iu_hi, min(n_u - 1, (int)floorf(fminf(fmaxf(u0, u1) + margin, (float)n_u))));
+        } else {
+          iu_all = true;
         }
-        for (int iu = iu_lo; iu <= iu_hi; ++iu) {
-          const float4 col = C[iu];
-          if ((int)__float_as_uint(col.x) != m) continue;
-          int ia;
-          float wfa, wca;
-          sample_axis<WF>(fplane, col.z, col.y, ha, ia, wfa, wca);
-          const float wA0 = (ia == va) ? wfa : ((ia + 1 == va) ? wca : 0.0f);
-          const float wA1 = (ia == va + 1) ? wfa : ((ia == va) ? wca : 0.0f);
-          if (wA0 == 0.0f && wA1 == 0.0f) continue;
-          // v of the column's rays on this plane: (A + P6 z) / W, affine in z
-          const float pa = __builtin_fmaf(fplane, col.z, col.y);
-          const float qx = (m == 0) ? fplane : pa, qy = (m == 0) ? pa : fplane;
-          const float A = __builtin_fmaf(P[4], qx, __builtin_fmaf(P[5], qy, P[7]));
-          const float W = __builtin_fmaf(P[8], qx, __builtin_fmaf(P[9], qy, P[11]));
-          const float4* R = RY + (size_t)iu * pitch;
-          float s0 = 0.0f, s1 = 0.0f;
-          int nc = 0;  // wave-uniform bound on the candidates per lane
-          int iv_lo = 0, iv_hi = n_v - 1;
-          if (W > 1.0e-6f) {
-            // rays whose axis-2 coordinate lies in [z - 1, z + 2) reach the pair
-            const float inv = __builtin_amdgcn_rcpf(W);
-            const float slope = P[6] * inv;  // pixels per voxel along z
-            const float base = A * inv;
-            const float va0 = __builtin_fmaf(slope, fz - 1.0f - e, base);
-            const float va1 = __builtin_fmaf(slope, fz + 2.0f + e, base);
-            const float lo = fminf(va0, va1) - margin, hi = fmaxf(va0, va1) + margin;
-            iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
-            iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
-            // an interval of length L holds at most floor(L) + 1 integers
-            nc = (int)(fabsf(slope) * (3.0f + 2.0f * e) + 2.0f * margin + 1.0e-3f) + 1;
-            if (!zin) iv_lo = n_v;  // reads the column's empty entries only
-          }
-          switch (nc) {
-            case 1:
-            case 2: pair_candidates<WF, 2>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-            case 3: pair_candidates<WF, 3>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-            case 4: pair_candidates<WF, 4>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-            case 5: pair_candidates<WF, 5>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-            case 6: pair_candidates<WF, 6>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-            case 7: pair_candidates<WF, 7>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-            case 8: pair_candidates<WF, 8>(R, iv_lo, plane, fplane, hz, fz, z, s0, s1); break;
-            default:
-              // long or unbounded candidate ranges: explicit per-lane loop
-              if (!zin) iv_hi = iv_lo - 1;
-              for (int iv = iv_lo; iv <= iv_hi; ++iv) {
-                const float4 r = R[iv];
-                const uint32_t mr = __float_as_uint(r.x);
-                const int i0 = (int)((mr >> 2) & 0x7fffu);
-                const int i1 = (int)(mr >> 17);
-                if (plane < i0 || plane >= i1) continue;
-                float b0, b1;
-                pair_weights<WF>(fplane, r.z, r.y, hz, fz, z, b0, b1);
-                s0 = __builtin_fmaf(r.w, b0, s0);
-                s1 = __builtin_fmaf(r.w, b1, s1);
+      }
+      if (iu_all) {
+        iu_lo = 0;
+        iu_hi = n_u - 1;
+      }
+      for (int iu = iu_lo; iu <= iu_hi; ++iu) {
+        const float4 col = C[iu];
+        if ((int)__float_as_uint(col.x) != m) continue;
+        int ia0, ia1;
+        float wfa0, wca0, wfa1, wca1;
+        sample_axis<WF>(fp0, col.z, col.y, ha, ia0, wfa0, wca0);
+        sample_axis<WF>(fp1, col.z, col.y, ha, ia1, wfa1, wca1);
+        // in-plane weights wA<plane><row> (rows va, va + 1)
+        const float wA00 = (ia0 == va) ? wfa0 : ((ia0 + 1 == va) ? wca0 : 0.0f);
+        const float wA01 = (ia0 == va + 1) ? wfa0 : ((ia0 == va) ? wca0 : 0.0f);
+        const float wA10 = !two ? 0.0f : ((ia1 == va) ? wfa1 : ((ia1 + 1 == va) ? wca1 : 0.0f));
+        const float wA11 = !two ? 0.0f : ((ia1 == va + 1) ? wfa1 : ((ia1 == va) ? wca1 : 0.0f));
+        if (wA00 == 0.0f && wA01 == 0.0f && wA10 == 0.0f && wA11 == 0.0f) continue;
+        // v of the column's rays on each plane: (A + P6 z) / W, affine in z
+        const float pa0 = __builtin_fmaf(fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
+        const float qx0 = (m == 0) ? fp0 : pa0, qy0 = (m == 0) ? pa0 : fp0;
+        const float qx1 = (m == 0) ? fp1 : pa1, qy1 = (m == 0) ? pa1 : fp1;
+        const float A0 = __builtin_fmaf(P[4], qx0, __builtin_fmaf(P[5], qy0, P[7]));
+        const float W0 = __builtin_fmaf(P[8], qx0, __builtin_fmaf(P[9], qy0, P[11]));
+        const float A1 = __builtin_fmaf(P[4], qx1, __builtin_fmaf(P[5], qy1, P[7]));
+        const float W1 = __builtin_fmaf(P[8], qx1, __builtin_fmaf(P[9], qy1, P[11]));
+        const float4* R = RY + (size_t)iu * pitch;
+        float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
+        int nc = 0;  // wave-uniform bound on the candidates per lane
+        int iv_lo = 0, iv_hi = n_v - 1;
+        if (W0 > 1.0e-6f && W1 > 1.0e-6f) {
+          // rays whose axis-2 coordinate lies in [z - 1, z + 2) on either plane
+          const float inv0 = __builtin_amdgcn_rcpf(W0), inv1 = __builtin_amdgcn_rcpf(W1);
+          const float sl0 = P[6] * inv0, sl1 = P[6] * inv1;  // pixels per voxel along z
+          const float b0 = A0 * inv0, b1 = A1 * inv1;
+          // span of the union window at axis-2 position zz (convex in zz)
+          auto window = [&](float zz, float& lo, float& hi) {
+            const float a0 = __builtin_fmaf(sl0, zz - 1.0f - e, b0);
+            const float a1 = __builtin_fmaf(sl0, zz + 2.0f + e, b0);
+            const float c0 = __builtin_fmaf(sl1, zz - 1.0f - e, b1);
+            const float c1 = __builtin_fmaf(sl1, zz + 2.0f + e, b1);
+            lo = fminf(fminf(a0, a1), fminf(c0, c1)) - margin;
+            hi = fmaxf(fmaxf(a0, a1), fmaxf(c0, c1)) + margin;
+          };
+          float lo, hi;
+          window(fz, lo, hi);
+          iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
+          iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
+          // an interval of length L holds at most floor(L) + 1 integers; the
+          // longest window of the wavefront is at one of its ends
+          float lo_a, hi_a, lo_b, hi_b;
+          const float zw = (float)(2 * zb * 64);
+          window(zw, lo_a, hi_a);
+          window(zw + 126.0f, lo_b, hi_b);
+          nc = (int)(fmaxf(hi_a - lo_a, hi_b - lo_b) + 1.0e-3f) + 1;
+          if (!zin) iv_lo = n_v;  // reads the column's empty entries only
+        }
+        switch (nc) {
+          case 1:
+          case 2: block_candidates<WF, 2>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 3: block_candidates<WF, 3>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 4: block_candidates<WF, 4>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 5: block_candidates<WF, 5>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 6: block_candidates<WF, 6>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 7: block_candidates<WF, 7>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 8: block_candidates<WF, 8>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          default:
+            // long or unbounded candidate ranges: explicit per-lane loop
+            if (!zin) iv_hi = iv_lo - 1;
+            for (int iv = iv_lo; iv <= iv_hi; ++iv) {
+              const float4 r = R[iv];
+              const uint32_t mr = __float_as_uint(r.x);
+              const int i0 = (int)((mr >> 2) & 0x7fffu);
+              const int i1 = (int)(mr >> 17);
+              float c0, c1;
+              if (p0 >= i0 && p0 < i1) {
+                pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, c0, c1);
+                s00 = __builtin_fmaf(r.w, c0, s00);
+                s01 = __builtin_fmaf(r.w, c1, s01);
               }
-              break;
-          }
-          // plane index dp and row index (0: va, 1: va + 1) of the block
-          if (m == 0) {
-            if (dp == 0) {
-              acc000 = __builtin_fmaf(wA0, s0, acc000); acc001 = __builtin_fmaf(wA0, s1, acc001);
-              acc010 = __builtin_fmaf(wA1, s0, acc010); acc011 = __builtin_fmaf(wA1, s1, acc011);
-            } else {
-              acc100 = __builtin_fmaf(wA0, s0, acc100); acc101 = __builtin_fmaf(wA0, s1, acc101);
-              acc110 = __builtin_fmaf(wA1, s0, acc110); acc111 = __builtin_fmaf(wA1, s1, acc111);
+              if (p0 + 1 >= i0 && p0 + 1 < i1) {
+                pair_weights<WF>(fp1, r.z, r.y, hz, fz, z, c0, c1);
+                s10 = __builtin_fmaf(r.w, c0, s10);
+                s11 = __builtin_fmaf(r.w, c1, s11);
+              }
             }
-          } else {
-            if (dp == 0) {
-              acc000 = __builtin_fmaf(wA0, s0, acc000); acc001 = __builtin_fmaf(wA0, s1, acc001);
-              acc100 = __builtin_fmaf(wA1, s0, acc100); acc101 = __builtin_fmaf(wA1, s1, acc101);
-            } else {
-              acc010 = __builtin_fmaf(wA0, s0, acc010); acc011 = __builtin_fmaf(wA0, s1, acc011);
-              acc110 = __builtin_fmaf(wA1, s0, acc110); acc111 = __builtin_fmaf(wA1, s1, acc111);
-            }
-          }
+            break;
+        }
+        // block voxel (plane p0 + d, row va + r, z + k) gets wA<d><r> s<d><k>
+        if (m == 0) {
+          acc000 = __builtin_fmaf(wA00, s00, acc000); acc001 = __builtin_fmaf(wA00, s01, acc001);
+          acc010 = __builtin_fmaf(wA01, s00, acc010); acc011 = __builtin_fmaf(wA01, s01, acc011);
+          acc100 = __builtin_fmaf(wA10, s10, acc100); acc101 = __builtin_fmaf(wA10, s11, acc101);
+          acc110 = __builtin_fmaf(wA11, s10, acc110); acc111 = __builtin_fmaf(wA11, s11, acc111);
+        } else {
+          acc000 = __builtin_fmaf(wA00, s00, acc000); acc001 = __builtin_fmaf(wA00, s01, acc001);
+          acc100 = __builtin_fmaf(wA01, s00, acc100); acc101 = __builtin_fmaf(wA01, s01, acc101);
+          acc010 = __builtin_fmaf(wA10, s10, acc010); acc011 = __builtin_fmaf(wA10, s11, acc011);
+          acc110 = __builtin_fmaf(wA11, s10, acc110); acc111 = __builtin_fmaf(wA11, s11, acc111);
         }
       }
     }
