@@ -746,7 +746,8 @@ struct BatchPlan {
   int* d_counter = nullptr;
   void* padded_all = nullptr;
   int n_items = 0;
-  int grid = 0;
+  // items are grouped by instance class; one persistent launch per class
+  std::vector<int> cls, cls_begin, cls_count, cls_grid;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   BatchInst* staging = nullptr;  // pinned
@@ -842,16 +843,27 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
   } catch (...) {
     return fail(GJP_ENOMEM, "batched: work list");
   }
-  // within an instance: groups of view_group views, each tile for all views
-  // of the group in turn (the single-instance launch order, for L2 reuse)
-  for (const auto& oc : order) {
-    const BatchInst& I = P->host[oc.inst];
-    const int K = std::max(1, I.a.view_group);
-    for (int v0 = 0; v0 < I.n_views; v0 += K) {
-      const int kg = std::min(K, I.n_views - v0);
-      for (int t = 0; t < I.a.tiles_per_view; ++t)
-        for (int v = v0; v < v0 + kg; ++v)
-          items.push_back(make_uint2((uint32_t)oc.inst | ((uint32_t)v << 12), (uint32_t)t));
+  // classes in a fixed order; within a class, instances longest first; within
+  // an instance, groups of view_group views, each tile for all views of the
+  // group in turn (the single-instance launch order, for L2 reuse)
+  for (int c = 0; c < gjp::kBatchClasses; ++c) {
+    const size_t begin = items.size();
+    for (const auto& oc : order) {
+      const BatchInst& I = P->host[oc.inst];
+      if (gjp::batch_class(I.dtype, I.weight, I.idx64) != c) continue;
+      const int K = std::max(1, I.a.view_group);
+      for (int v0 = 0; v0 < I.n_views; v0 += K) {
+        const int kg = std::min(K, I.n_views - v0);
+        for (int t = 0; t < I.a.tiles_per_view; ++t)
+          for (int v = v0; v < v0 + kg; ++v)
+            items.push_back(make_uint2((uint32_t)oc.inst | ((uint32_t)v << 12), (uint32_t)t));
+      }
+    }
+    if (items.size() > begin) {
+      P->cls.push_back(c);
+      P->cls_begin.push_back((int)begin);
+      P->cls_count.push_back((int)(items.size() - begin));
+      P->cls_grid.push_back(gjp::batched_grid_size(c));
     }
   }
   P->n_items = (int)items.size();
@@ -861,10 +873,10 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
                     hipMemcpyHostToDevice),
           "batched: items copy");
   GJP_HIP(hipMalloc(&P->d_insts, (size_t)n * sizeof(BatchInst)), "batched: descriptors");
-  GJP_HIP(hipMalloc(&P->d_counter, sizeof(int)), "batched: queue");
+  GJP_HIP(hipMalloc(&P->d_counter, std::max<size_t>(1, P->cls.size()) * sizeof(int)),
+          "batched: queues");
   GJP_HIP(hipHostMalloc(&P->staging, (size_t)n * sizeof(BatchInst), 0), "batched: staging");
   GJP_HIP(hipEventCreateWithFlags(&P->staged, hipEventDisableTiming), "batched: event");
-  P->grid = gjp::batched_grid_size();
   // capture pad + queue reset + persistent kernel once
   hipStream_t cap;
   GJP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "batched: capture stream");
@@ -872,10 +884,11 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
   int st = GJP_OK;
   if (e == hipSuccess) {
     st = gjp::launch_batched_pad(P->d_insts, n, cap);
-    if (st == GJP_OK) st = gjp::launch_reset_counter(P->d_counter, cap);
-    if (st == GJP_OK)
-      st = gjp::launch_batched_forward(P->d_insts, P->d_items, P->n_items, P->d_counter,
-                                       P->grid, cap);
+    if (st == GJP_OK) st = gjp::launch_zero_ints(P->d_counter, (int)P->cls.size(), cap);
+    for (size_t k = 0; k < P->cls.size() && st == GJP_OK; ++k)
+      st = gjp::launch_batched_forward(P->d_insts, P->d_items + P->cls_begin[k],
+                                       P->cls_count[k], P->d_counter + k, P->cls_grid[k],
+                                       P->cls[k], cap);
     const hipError_t e2 = hipStreamEndCapture(cap, &P->graph);
     if (e2 != hipSuccess && st == GJP_OK) st = hip_fail(e2, "batched: end capture");
   } else {

@@ -105,10 +105,12 @@ struct BatchInst {
   long long padded_elems;
 };
 int launch_batched_pad(const BatchInst* d_insts, int n_inst, hipStream_t s);
-int launch_reset_counter(int* counter, hipStream_t s);
+// Instance class of the batched launch: (dtype * 2 + weight) * 2 + idx64.
+inline int batch_class(int dtype, int weight, int idx64) { return (dtype * 2 + weight) * 2 + idx64; }
+constexpr int kBatchClasses = 12;
 int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
-                           int* counter, int grid, hipStream_t s);
-int batched_grid_size();
+                           int* counter, int grid, int cls, hipStream_t s);
+int batched_grid_size(int cls);
 
 size_t dtype_size(int dtype);
 

@@ -758,7 +758,7 @@ __host__ __device__ inline void gather_grid(const int* n, int& nzb, int& nyb, in
 // two in-plane rows: one candidate list per column serves both rows (the
 // column's in-plane weight differs per row, the axis-2 weights do not).
 template <int WF>
-__global__ __launch_bounds__(256) void adj_gather_sep_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void adj_gather_sep_kernel(
     const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
     const float4* __restrict__ rays, const float4* __restrict__ cols,
     const int* __restrict__ mask, int view0, int c0, int n_chunk, int accumulate,
@@ -980,19 +980,11 @@ __global__ void zero_ints_kernel(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
-__global__ void reset_counter_kernel(int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
-}
-
-template <typename T, int WF>
-__device__ __forceinline__ void batched_item_t(const FwdArgs& a, int idx64, int view, int t) {
-  if (idx64)
-    fwd_tile<T, WF, true>(a, view, t);
-  else
-    fwd_tile<T, WF, false>(a, view, t);
-}
-
-__global__ __launch_bounds__(256) void batched_fwd_kernel(const BatchInst* __restrict__ insts,
+// Persistent batched forward for one instance class (storage type T, weight
+// WF, addressing IDX64): each workgroup pulls (instance, view, tile) items
+// from the class's queue until it is drained.
+template <typename T, int WF, bool IDX64>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void batched_fwd_kernel(const BatchInst* __restrict__ insts,
                                                           const uint2* __restrict__ items,
                                                           int n_items, int* __restrict__ counter) {
   __shared__ int s_item;
@@ -1005,18 +997,7 @@ __global__ __launch_bounds__(256) void batched_fwd_kernel(const BatchInst* __res
     const uint2 it = items[item];
     const int inst = (int)(it.x & 0xfffu);
     const int view = (int)(it.x >> 12);
-    const int t = (int)it.y;
-    const BatchInst& I = insts[inst];
-    const FwdArgs a = I.a;
-    const int sel = I.dtype * 2 + I.weight;
-    switch (sel) {
-      case 0: batched_item_t<float, W_LINEAR>(a, I.idx64, view, t); break;
-      case 1: batched_item_t<float, W_SPLINE>(a, I.idx64, view, t); break;
-      case 2: batched_item_t<bf16_t, W_LINEAR>(a, I.idx64, view, t); break;
-      case 3: batched_item_t<bf16_t, W_SPLINE>(a, I.idx64, view, t); break;
-      case 4: batched_item_t<f16_t, W_LINEAR>(a, I.idx64, view, t); break;
-      default: batched_item_t<f16_t, W_SPLINE>(a, I.idx64, view, t); break;
-    }
+    fwd_tile<T, WF, IDX64>(insts[inst].a, view, (int)it.y);
   }
 }
 
@@ -1135,26 +1116,56 @@ int launch_zero_ints(int* p, int n, hipStream_t s) {
   return check_launch("zero kernel");
 }
 
-int launch_reset_counter(int* counter, hipStream_t s) {
-  reset_counter_kernel<<<1, 64, 0, s>>>(counter);
-  return check_launch("queue reset kernel");
-}
-
-int batched_grid_size() {
+template <typename T, int WF, bool IDX64>
+static int batched_grid_t() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_fwd_kernel, 256, 0) !=
-          hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_fwd_kernel<T, WF, IDX64>, 256,
+                                                   0) != hipSuccess ||
       per <= 0)
     per = 4;
   return cus * per;
 }
 
+template <typename T, int WF, bool IDX64>
+static void launch_batched_t(const BatchInst* d_insts, const uint2* d_items, int n_items,
+                             int* counter, int grid, hipStream_t s) {
+  batched_fwd_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, n_items, counter);
+}
+
+// class = (dtype * 2 + weight) * 2 + idx64
+#define GJP_BATCH_CLASSES(X)                                                        \
+  X(0, float, W_LINEAR, false) X(1, float, W_LINEAR, true) X(2, float, W_SPLINE, false) \
+  X(3, float, W_SPLINE, true) X(4, bf16_t, W_LINEAR, false) X(5, bf16_t, W_LINEAR, true) \
+  X(6, bf16_t, W_SPLINE, false) X(7, bf16_t, W_SPLINE, true) X(8, f16_t, W_LINEAR, false) \
+  X(9, f16_t, W_LINEAR, true) X(10, f16_t, W_SPLINE, false) X(11, f16_t, W_SPLINE, true)
+
+int batched_grid_size(int cls) {
+  switch (cls) {
+#define GJP_CASE(k, T, W, I) \
+  case k:                    \
+    return batched_grid_t<T, W, I>();
+    GJP_BATCH_CLASSES(GJP_CASE)
+#undef GJP_CASE
+    default:
+      return 1024;
+  }
+}
+
 int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
-                           int* counter, int grid, hipStream_t s) {
-  batched_fwd_kernel<<<grid, 256, 0, s>>>(d_insts, d_items, n_items, counter);
+                           int* counter, int grid, int cls, hipStream_t s) {
+  switch (cls) {
+#define GJP_CASE(k, T, W, I)                                               \
+  case k:                                                                  \
+    launch_batched_t<T, W, I>(d_insts, d_items, n_items, counter, grid, s); \
+    break;
+    GJP_BATCH_CLASSES(GJP_CASE)
+#undef GJP_CASE
+    default:
+      return set_error(-4, "batched: unknown instance class");
+  }
   return check_launch("batched forward kernel");
 }
 
