@@ -86,9 +86,12 @@ gjp_status gjp_destroy_geometry(gjp_geometry *g);
    d_vol: device, n0*n1*n2 elements of `vol_dtype` (gjp_dtype), C order,
    aligned to its element size. d_sino: device, n_views*n_u*n_v floats,
    overwritten. BF16/FP16 volumes are widened to FP32 in registers; the
-   accumulation is FP32 in every case. A zero-padded copy of the volume is
-   taken from the stream-ordered pool for the duration of the call.
-   Errors: GJP_EINVAL (null pointer, unknown dtype), GJP_ENOMEM, GJP_EHIP. */
+   accumulation is FP32 in every case. Two zero-padded pair copies of the
+   volume (about 4x its size) are taken from the stream-ordered pool for the
+   duration of the call. The volume must be finite.
+   Errors: GJP_EINVAL (null pointer, unknown dtype), GJP_EUNSUPPORTED (a
+   volume plane above about 32 MiB per pair copy, beyond 2048^2 FP32),
+   GJP_ENOMEM, GJP_EHIP. */
 gjp_status gjp_forward_project(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
                                float *d_sino, void *stream);
 

@@ -5,20 +5,21 @@
 // lane index runs along detector v, the direction parallel to the rotation
 // axis and to the fastest volume index n2. For a circular trajectory the
 // driving axis is then 0 or 1 (never the fastest index, as the paper's
-// Algorithm 1 caption recommends for cache efficiency), the 64 lanes of a
-// wavefront share the same transverse row on every plane, and the two row
-// reads of a sample are contiguous voxel pairs (z, z+1) fetched as one 8-byte
-// (FP32) or 4-byte (16-bit) load. The volume is read from a zero-padded copy
-// (one voxel on every side), so the sampling loop has no bounds tests.
+// Algorithm 1 caption recommends for cache efficiency) and the 64 lanes of a
+// wavefront share the same transverse row on every plane. The volume is read
+// from zero-padded pair copies (one voxel of border on every side; each
+// element also holds its neighbour along one transverse axis), so the four
+// in-plane neighbours of a sample arrive in one wide load and the sampling
+// loop has no bounds tests.
 //
 // Adjoint: exact transpose of the forward. A table pass stores, per ray of a
 // chunk of views, the setup the forward computes (driving axis, sample range,
 // single-precision coefficients) and the sinogram value times the step length.
-// A splat pass gives each workgroup a voxel tile in LDS; the rays of the view
-// chunk that can touch the tile recompute their samples on the tile's planes
-// with the same `sample_axis` code as the forward and add the weighted
-// contributions into LDS (waves own disjoint planes, so the sum order is
-// fixed). Each voxel is written to memory once per chunk; no global atomics.
+// For circular trajectories a voxel-driven gather evaluates, for each voxel
+// block, the few rays of each nearby detector column that reach it; otherwise
+// a splat pass accumulates ray samples into a voxel tile held in LDS. Both
+// recompute the forward's weights, sum in a fixed order and write each voxel
+// once per launch; no global atomics.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
