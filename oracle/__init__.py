@@ -27,6 +27,7 @@ _LIB = None
 
 CONE, PARALLEL = 0, 1
 W_LINEAR, W_SPLINE = 0, 1
+CLIP_CYLINDER = 1
 
 _i32p = ctypes.POINTER(ctypes.c_int)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -40,7 +41,8 @@ def lib():
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
             _build.build()
         L = ctypes.CDLL(path)
-        geo = [_i32p, _f64p, _f64p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int, ctypes.c_int]
+        geo = [_i32p, _f64p, _f64p, ctypes.c_int, ctypes.c_int, _f64p, ctypes.c_int, ctypes.c_int,
+               ctypes.c_int]
         L.gjo_views_circular_cone.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int, _f64p]
@@ -100,6 +102,7 @@ class Geometry:
     voxel_size: tuple = (1.0, 1.0, 1.0)
     center: tuple = (0.0, 0.0, 0.0)
     weight: int = W_LINEAR
+    clip_cylinder: bool = False  # Sec. IV-C sample range clipping
 
     def __post_init__(self):
         self.views = np.ascontiguousarray(self.views, dtype=np.float64).reshape(-1, 12)
@@ -114,7 +117,7 @@ class Geometry:
     def _args(self):
         return (_p(self._shape, _i32p), _p(self._vs, _f64p), _p(self._ctr, _f64p),
                 int(self.beam), self.n_views, _p(self.views, _f64p), int(self.n_u),
-                int(self.n_v))
+                int(self.n_v), CLIP_CYLINDER if self.clip_cylinder else 0)
 
 
 def _vol_arg(vol):
@@ -181,7 +184,8 @@ def ray_info(g: Geometry, view: int, iu: int, iv: int):
 
 
 def geometry_for(cfg, weight: int = W_LINEAR) -> Geometry:
-    """Oracle geometry for a workload configuration (circular trajectory)."""
+    """Oracle geometry for a workload configuration (circular trajectory;
+    cylinder clipping when the configuration asks for it)."""
     if cfg.beam == "cone":
         views = views_circular_cone(cfg.n_views, cfg.sod, cfg.sdd, cfg.pitch_u, cfg.pitch_v,
                                     cfg.n_u, cfg.n_v)
@@ -189,4 +193,5 @@ def geometry_for(cfg, weight: int = W_LINEAR) -> Geometry:
     else:
         views = views_parallel(cfg.n_views, cfg.pitch_u, cfg.pitch_v, cfg.n_u, cfg.n_v)
         beam = PARALLEL
-    return Geometry(tuple(cfg.shape), views, cfg.n_u, cfg.n_v, beam=beam, weight=weight)
+    return Geometry(tuple(cfg.shape), views, cfg.n_u, cfg.n_v, beam=beam, weight=weight,
+                    clip_cylinder=bool(getattr(cfg, "clip_cylinder", False)))

@@ -29,6 +29,12 @@
  *     applies it per term; only rounding differs). With non-unit voxels it
  *     is the world-space step || r~ * voxel_size ||.
  *   - A ray with r = 0 (source on a pixel) has no direction: its value is 0.
+ *   - Cylinder clipping (Sec. IV-C: the first sample and the sample count
+ *     follow the ray-cylinder instead of the ray-box intersection), when
+ *     GJO_CLIP_CYLINDER is set: a sample also needs its axis-0/axis-1
+ *     position strictly inside the circle of radius min(N0, N1) / 2 about
+ *     ((N0 - 1) / 2, (N1 - 1) / 2), the cylinder inscribed in the grid box
+ *     with its axis along the rotation axis (axis 2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -45,6 +51,7 @@ static const double GJO_PI = 3.14159265358979323846;
 #define GJO_PARALLEL 1
 #define GJO_W_LINEAR 0
 #define GJO_W_SPLINE 1
+#define GJO_CLIP_CYLINDER 1
 
 /* ------------------------------------------------------------------ */
 /* Projection geometry: circular trajectory about the third axis.       */
@@ -112,6 +119,9 @@ typedef struct {
   int n_views, n_u, n_v;
   const double *views; /* world units */
   int weight;
+  int clip;            /* cylinder clipping (Sec. IV-C) */
+  double cyl_c[2];     /* cylinder axis position on axes 0 and 1 */
+  double cyl_r2;       /* squared radius */
 } gjo_geom;
 
 typedef struct {
@@ -209,6 +219,10 @@ static int sample_at(const gjo_geom *g, const gjo_ray *ray, int i, gjo_sample *s
   p[m] = (double)i;
   for (int k = 0; k < 3; ++k)
     if (!(p[k] > -1.0 && p[k] < (double)g->n[k])) return 0;
+  if (g->clip) {
+    const double dx = p[0] - g->cyl_c[0], dy = p[1] - g->cyl_c[1];
+    if (!(dx * dx + dy * dy < g->cyl_r2)) return 0;
+  }
   for (int k = 0; k < 3; ++k) {
     double f = floor(p[k]);
     double c = ceil(p[k]);
@@ -260,7 +274,7 @@ static void ray_adjoint(const gjo_geom *g, double y, int view, int iu, int iv, d
 
 static int make_geom(gjo_geom *g, const int *shape, const double *voxel_size,
                      const double *center, int beam, int n_views, const double *views, int n_u,
-                     int n_v, int weight) {
+                     int n_v, int flags, int weight) {
   if (!shape || !voxel_size || !center || !views) return -1;
   for (int k = 0; k < 3; ++k) {
     if (shape[k] <= 0 || !(voxel_size[k] > 0.0)) return -1;
@@ -277,6 +291,12 @@ static int make_geom(gjo_geom *g, const int *shape, const double *voxel_size,
   g->n_v = n_v;
   g->views = views;
   g->weight = weight;
+  if (flags & ~GJO_CLIP_CYLINDER) return -1;
+  g->clip = (flags & GJO_CLIP_CYLINDER) != 0;
+  g->cyl_c[0] = 0.5 * (double)(g->n[0] - 1);
+  g->cyl_c[1] = 0.5 * (double)(g->n[1] - 1);
+  const double rad = 0.5 * (double)(g->n[0] < g->n[1] ? g->n[0] : g->n[1]);
+  g->cyl_r2 = rad * rad;
   return 0;
 }
 
@@ -303,10 +323,10 @@ void gjo_set_num_threads(int n) {
 /* Forward projection of the whole sinogram. vol: n0*n1*n2 (C order, f64 if
    vol_dt == 0, f32 if 1); sino: n_views*n_u*n_v doubles, v fastest. */
 int gjo_forward(const int *shape, const double *voxel_size, const double *center, int beam,
-                int n_views, const double *views, int n_u, int n_v, int weight,
+                int n_views, const double *views, int n_u, int n_v, int flags, int weight,
                 const void *vol, int vol_dt, double *sino) {
   gjo_geom g;
-  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, weight) != 0 ||
+  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, flags, weight) != 0 ||
       !vol || !sino)
     return -1;
   const long long n_rays = (long long)n_views * n_u * n_v;
@@ -321,11 +341,11 @@ int gjo_forward(const int *shape, const double *voxel_size, const double *center
 
 /* Forward projection of a list of rays: rays = n_rays x (view, iu, iv). */
 int gjo_forward_rays(const int *shape, const double *voxel_size, const double *center, int beam,
-                     int n_views, const double *views, int n_u, int n_v, int weight,
+                     int n_views, const double *views, int n_u, int n_v, int flags, int weight,
                      const void *vol, int vol_dt, long long n_rays, const int *rays,
                      double *out, long long *counts) {
   gjo_geom g;
-  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, weight) != 0 ||
+  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, flags, weight) != 0 ||
       !vol || !rays || !out)
     return -1;
   for (long long r = 0; r < n_rays; ++r) {
@@ -347,10 +367,10 @@ int gjo_forward_rays(const int *shape, const double *voxel_size, const double *c
    Views are split over threads, each accumulating into a private volume;
    the private volumes are summed in thread order. */
 int gjo_adjoint(const int *shape, const double *voxel_size, const double *center, int beam,
-                int n_views, const double *views, int n_u, int n_v, int weight,
+                int n_views, const double *views, int n_u, int n_v, int flags, int weight,
                 const double *sino, double *vol) {
   gjo_geom g;
-  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, weight) != 0 ||
+  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, flags, weight) != 0 ||
       !vol || !sino)
     return -1;
   const size_t nvox = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -389,9 +409,9 @@ int gjo_adjoint(const int *shape, const double *voxel_size, const double *center
 
 /* Number of in-volume samples (ray, plane) over the whole sinogram. */
 long long gjo_count_samples(const int *shape, const double *voxel_size, const double *center,
-                            int beam, int n_views, const double *views, int n_u, int n_v) {
+                            int beam, int n_views, const double *views, int n_u, int n_v, int flags) {
   gjo_geom g;
-  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, 0) != 0)
+  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, flags, 0) != 0)
     return -1;
   const long long n_rays = (long long)n_views * n_u * n_v;
   long long total = 0;
@@ -412,10 +432,10 @@ long long gjo_count_samples(const int *shape, const double *voxel_size, const do
 
 /* Per-ray driving axis and step length (for tests of the setup step). */
 int gjo_ray_info(const int *shape, const double *voxel_size, const double *center, int beam,
-                 int n_views, const double *views, int n_u, int n_v, int view, int iu, int iv,
+                 int n_views, const double *views, int n_u, int n_v, int flags, int view, int iu, int iv,
                  int *m_out, double *len_out, double *rt_out) {
   gjo_geom g;
-  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, 0) != 0)
+  if (make_geom(&g, shape, voxel_size, center, beam, n_views, views, n_u, n_v, flags, 0) != 0)
     return -1;
   gjo_ray ray;
   ray_setup(&g, view, iu, iv, &ray);
