@@ -63,8 +63,17 @@ typedef struct {
   int32_t beam;           /* gjp_beam */
   const double *views;    /* host, n_views x 12 doubles (world units); copied */
   int32_t weight;         /* gjp_weight */
-  uint32_t flags;         /* reserved, must be 0 */
+  uint32_t flags;         /* 0 or GJP_CLIP_CYLINDER */
 } gjp_geometry_desc;
+
+/* gjp_geometry_desc.flags: clip every ray's sample range to the cylinder
+   inscribed in the grid box (Sec. IV-C: the first sample and the number of
+   samples follow the ray-cylinder instead of the ray-box intersection). The
+   cylinder's axis is the rotation axis (axis 2) through ((n0-1)/2, (n1-1)/2)
+   in grid coordinates, its radius min(n0, n1)/2 voxels; a sample counts only
+   if its axis-0/axis-1 position lies strictly inside. Forward, adjoint and
+   sample count all use the clipped range. */
+#define GJP_CLIP_CYLINDER 1u
 
 typedef struct gjp_geometry gjp_geometry; /* opaque, immutable after creation */
 
@@ -73,7 +82,7 @@ typedef struct gjp_geometry gjp_geometry; /* opaque, immutable after creation */
    vectors and converts them to grid units; device copies are made on first
    use on each device. *out receives the handle (caller destroys it).
    Errors: GJP_EINVAL for a null pointer, a non-positive size, a
-   non-positive voxel size, an unknown beam/weight, non-zero flags, a
+   non-positive voxel size, an unknown beam/weight, unknown flags, a
    non-finite view vector, or more than 32767 voxels along an axis;
    GJP_ENOMEM if the copy cannot be allocated. */
 gjp_status gjp_create_geometry(const gjp_geometry_desc *desc, gjp_geometry **out);

@@ -16,6 +16,7 @@ GJP_OK, GJP_EINVAL, GJP_ENOMEM, GJP_EHIP, GJP_EUNSUPPORTED = 0, -1, -2, -3, -4
 F32, BF16, F16 = 0, 1, 2
 CONE, PARALLEL = 0, 1
 W_LINEAR, W_SPLINE = 0, 1
+CLIP_CYLINDER = 1  # gjp_geometry_desc.flags
 
 # Every symbol include/gjp.h declares.
 EXPORTS = (

@@ -312,7 +312,8 @@ extern "C" gjp_status gjp_create_geometry(const gjp_geometry_desc* d, gjp_geomet
     return fail(GJP_EINVAL, "gjp_create_geometry: unknown beam");
   if (d->weight != GJP_W_LINEAR && d->weight != GJP_W_SPLINE)
     return fail(GJP_EINVAL, "gjp_create_geometry: unknown weight function");
-  if (d->flags != 0) return fail(GJP_EINVAL, "gjp_create_geometry: flags must be 0");
+  if ((d->flags & ~GJP_CLIP_CYLINDER) != 0)
+    return fail(GJP_EINVAL, "gjp_create_geometry: unknown flags");
   if (!d->views) return fail(GJP_EINVAL, "gjp_create_geometry: views is null");
   const size_t nv = (size_t)d->n_views;
   if ((unsigned long long)d->n_views * d->n_u * d->n_v > (1ull << 46))
@@ -345,6 +346,13 @@ extern "C" gjp_status gjp_create_geometry(const gjp_geometry_desc* d, gjp_geomet
     memcpy(&g->gg.hi[k], &bits, 4);
   }
   g->gg.beam = d->beam;
+  g->gg.clip = (d->flags & GJP_CLIP_CYLINDER) ? 1 : 0;
+  g->gg.cyl[0] = 0.5 * (double)(g->gg.n[0] - 1);
+  g->gg.cyl[1] = 0.5 * (double)(g->gg.n[1] - 1);
+  {
+    const double rad = 0.5 * (double)(g->gg.n[0] < g->gg.n[1] ? g->gg.n[0] : g->gg.n[1]);
+    g->gg.cyl_r2 = rad * rad;
+  }
   g->n_views = d->n_views;
   g->n_u = d->n_u;
   g->n_v = d->n_v;

@@ -30,6 +30,12 @@ struct GridGeom {
   double vs[3];    // voxel size (world units per grid step)
   float hi[3];     // largest float below n[k]: upper clamp of sample coordinates
   int beam;
+  // Cylinder clipping of the sample range (Sec. IV-C): a sample also needs
+  // (p_0 - cyl[0])^2 + (p_1 - cyl[1])^2 < cyl_r2 (the cylinder inscribed in
+  // the grid box, axis along axis 2).
+  int clip;
+  double cyl[2];
+  double cyl_r2;
 };
 
 // Row pitch (elements) of the zero-padded volume copy: n2 + 2 rounded up to
@@ -123,7 +129,7 @@ GJP_HD void ray_setup(const double* __restrict__ v, const GridGeom& G, int iu, i
   R.gb = (float)g[b];
 
   // Sample range: analytic estimate, then the exact predicate at the ends.
-  // The predicate is monotone in i on each axis, so the samples form one run.
+  // Box and cylinder are convex, so the samples form one run.
   const int nm = G.n[m];
   double lo_a, hi_a, lo_b, hi_b;
   axis_interval(s[a], s[m], g[a], G.n[a], lo_a, hi_a);
@@ -132,17 +138,60 @@ GJP_HD void ray_setup(const double* __restrict__ v, const GridGeom& G, int iu, i
   double hi = hi_a < hi_b ? hi_a : hi_b;
   lo = lo < -2.0 ? -2.0 : (lo > (double)nm + 1.0 ? (double)nm + 1.0 : lo);
   hi = hi < -2.0 ? -2.0 : (hi > (double)nm + 1.0 ? (double)nm + 1.0 : hi);
+  const double sa = s[a], sb = s[b], ga = g[a], gb = g[b];
+  if (G.clip) {
+    // the cylinder cross-section coordinates (p_0, p_1) are affine in the
+    // plane index: p = u + w i; the chord is where |u + w i - c|^2 < r^2
+    double u0, w0, u1, w1;
+    if (m == 0) {
+      u0 = 0.0; w0 = 1.0; u1 = sa + neg_sm * ga; w1 = ga;
+    } else if (m == 1) {
+      u0 = sa + neg_sm * ga; w0 = ga; u1 = 0.0; w1 = 1.0;
+    } else {
+      u0 = sa + neg_sm * ga; w0 = ga; u1 = sb + neg_sm * gb; w1 = gb;
+    }
+    const double e0 = u0 - G.cyl[0], e1 = u1 - G.cyl[1];
+    const double qa = w0 * w0 + w1 * w1, qb = w0 * e0 + w1 * e1;
+    const double qc = e0 * e0 + e1 * e1 - G.cyl_r2;
+    double clo = -1.0e300, chi = 1.0e300;
+    if (qa > 0.0) {
+      const double disc = qb * qb - qa * qc;
+      if (disc > 0.0) {
+        const double sq = sqrt(disc);
+        clo = (-qb - sq) / qa;
+        chi = (-qb + sq) / qa;
+      } else {
+        clo = 1.0;  // empty (the exact predicate decides the ends below)
+        chi = -1.0;
+      }
+    } else if (qc >= 0.0) {
+      clo = 1.0;
+      chi = -1.0;
+    }
+    // widened by a plane on each side; the exact predicate trims the ends
+    lo = lo > clo - 1.0 ? lo : clo - 1.0;
+    hi = hi < chi + 1.0 ? hi : chi + 1.0;
+    if (hi < lo) hi = lo;
+  }
   int i0 = (int)floor(lo) + 1;
   int i1 = (int)ceil(hi);
   i0 = i0 < 0 ? 0 : (i0 > nm ? nm : i0);
   i1 = i1 < 0 ? 0 : (i1 > nm ? nm : i1);
   if (i1 < i0) i1 = i0;
-  // inside_both's predicate on the plane index held as an exact double next
-  // to the integer (same arithmetic; keeps the device register count low)
-  const double sa = s[a], sb = s[b], ga = g[a], gb = g[b];
+  // inside_both's predicate (and the cylinder test) on the plane index held
+  // as an exact double next to the integer (same arithmetic; keeps the
+  // device register count low)
   const int na = G.n[a], nb = G.n[b];
+  const int clip = G.clip;
+  const double cx = G.cyl[0], cy = G.cyl[1], cr2 = G.cyl_r2;
   auto inside = [=](double di) {
-    return inside_axis(sa, neg_sm, ga, di, na) && inside_axis(sb, neg_sm, gb, di, nb);
+    const double pa = sa + (neg_sm + di) * ga, pb = sb + (neg_sm + di) * gb;
+    if (!(pa > -1.0 && pa < (double)na && pb > -1.0 && pb < (double)nb)) return false;
+    if (!clip) return true;
+    const double px = (m == 0) ? di : pa;
+    const double py = (m == 0) ? pa : ((m == 1) ? di : pb);
+    const double dx = px - cx, dy = py - cy;
+    return dx * dx + dy * dy < cr2;
   };
   double d0 = (double)i0;
   while (i0 < i1 && !inside(d0)) {

@@ -43,7 +43,7 @@ class Geometry:
 
     def __init__(self, shape: Sequence[int], views: np.ndarray, n_u: int, n_v: int,
                  beam="cone", voxel_size=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0),
-                 weight="linear"):
+                 weight="linear", clip_cylinder=False):
         self.shape = tuple(int(s) for s in shape)
         self.views = np.ascontiguousarray(views, dtype=np.float64).reshape(-1, 12)
         self.n_u, self.n_v = int(n_u), int(n_v)
@@ -51,6 +51,7 @@ class Geometry:
         self.weight = _WEIGHTS[weight]
         self.voxel_size = tuple(float(x) for x in voxel_size)
         self.center = tuple(float(x) for x in center)
+        self.clip_cylinder = bool(clip_cylinder)
         d = _lib.GeometryDesc()
         for k in range(3):
             d.vol_shape[k] = self.shape[k]
@@ -61,29 +62,32 @@ class Geometry:
         d.beam = self.beam
         d.views = _f64p(self.views)
         d.weight = self.weight
-        d.flags = 0
+        d.flags = _lib.CLIP_CYLINDER if self.clip_cylinder else 0
         h = ctypes.c_void_p()
         check(lib().gjp_create_geometry(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
 
     @classmethod
     def circular_cone(cls, shape, n_views, n_u, n_v, sod, sdd, pitch_u=1.0, pitch_v=1.0,
-                      weight="linear"):
+                      weight="linear", clip_cylinder=False):
         v = views_circular_cone(n_views, sod, sdd, pitch_u, pitch_v, n_u, n_v)
-        return cls(shape, v, n_u, n_v, beam="cone", weight=weight)
+        return cls(shape, v, n_u, n_v, beam="cone", weight=weight, clip_cylinder=clip_cylinder)
 
     @classmethod
-    def parallel(cls, shape, n_views, n_u, n_v, pitch_u=1.0, pitch_v=1.0, weight="linear"):
+    def parallel(cls, shape, n_views, n_u, n_v, pitch_u=1.0, pitch_v=1.0, weight="linear",
+                 clip_cylinder=False):
         v = views_parallel(n_views, pitch_u, pitch_v, n_u, n_v)
-        return cls(shape, v, n_u, n_v, beam="parallel", weight=weight)
+        return cls(shape, v, n_u, n_v, beam="parallel", weight=weight,
+                   clip_cylinder=clip_cylinder)
 
     @classmethod
     def from_config(cls, cfg, weight="linear"):
+        clip = bool(getattr(cfg, "clip_cylinder", False))
         if cfg.beam == "cone":
             return cls.circular_cone(cfg.shape, cfg.n_views, cfg.n_u, cfg.n_v, cfg.sod, cfg.sdd,
-                                     cfg.pitch_u, cfg.pitch_v, weight=weight)
+                                     cfg.pitch_u, cfg.pitch_v, weight=weight, clip_cylinder=clip)
         return cls.parallel(cfg.shape, cfg.n_views, cfg.n_u, cfg.n_v, cfg.pitch_u, cfg.pitch_v,
-                            weight=weight)
+                            weight=weight, clip_cylinder=clip)
 
     @property
     def n_views(self) -> int:

@@ -59,7 +59,7 @@ def test_error_paths_without_gpu(gjp):
     h = ctypes.c_void_p()
     for kw in ({"shape": (0, 8, 8)}, {"shape": (8, -1, 8)}, {"shape": (8, 8, 40000)},
                {"vs": 0.0}, {"n_views": 0}, {"n_u": 0}, {"beam": 7}, {"weight": 3},
-               {"flags": 1}, {"views": None}):
+               {"flags": 2}, {"views": None}):
         d, keep = desc(**kw)
         st = L.gjp_create_geometry(ctypes.byref(d), ctypes.byref(h))
         assert st == _lib.GJP_EINVAL, kw
@@ -145,3 +145,32 @@ def test_sample_count_anisotropic_voxels(gjp, oracle_mod):
     G = gjp.Geometry(shape, views, 15, 17, voxel_size=vs, center=ctr)
     og = oracle_mod.Geometry(shape, views, 15, 17, voxel_size=vs, center=ctr)
     assert G.count_samples() == oracle_mod.count_samples(og)
+
+
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+def test_sample_count_with_cylinder_clipping(gjp, oracle_mod, beam):
+    # the kernels' range setup (analytic chord + exact end predicate) against
+    # the oracle's per-plane test; non-square cross-section, random rays
+    shape = (19, 14, 11)
+    n_views, n_u, n_v = 36, 23, 17
+    if beam == "cone":
+        views = workloads.random_cone_views(63, n_views, shape, n_u, n_v)
+        b = oracle_mod.CONE
+    else:
+        views = workloads.random_parallel_views(63, n_views, shape, n_u, n_v)
+        b = oracle_mod.PARALLEL
+    G = gjp.Geometry(shape, views, n_u, n_v, beam=beam, clip_cylinder=True)
+    og = oracle_mod.Geometry(shape, views, n_u, n_v, beam=b, clip_cylinder=True)
+    n_clip = G.count_samples()
+    assert n_clip == oracle_mod.count_samples(og)
+    assert n_clip < gjp.Geometry(shape, views, n_u, n_v, beam=beam).count_samples()
+
+
+def test_sample_count_with_cylinder_clipping_circular(gjp, oracle_mod):
+    for cfg in (workloads.WorkloadConfig("k", (32, 32, 24), 40, 48, 36, beam="cone", sod=150.0,
+                                         sdd=300.0, pitch_u=1.5, pitch_v=1.5,
+                                         clip_cylinder=True),
+                workloads.WorkloadConfig("q", (30, 26, 10), 33, 40, 12, beam="parallel",
+                                         pitch_u=0.9, pitch_v=1.1, clip_cylinder=True)):
+        G = gjp.Geometry.from_config(cfg)
+        assert G.count_samples() == oracle_mod.count_samples(oracle_mod.geometry_for(cfg))

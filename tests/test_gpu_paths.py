@@ -200,6 +200,12 @@ def test_full_c3_forward(gjp, oracle_mod):
     _full_config_check(gjp, oracle_mod, "c3", 3000)
 
 
+def test_full_t1_forward_clipped(gjp, oracle_mod):
+    """The paper's speed geometry (512^3, 512^2 detector, 10 degree cone, 360
+    views, sample range clipped to the inscribed cylinder), FP32 and BF16."""
+    _full_config_check(gjp, oracle_mod, "t1", 3000, dtypes=("f32", "bf16"))
+
+
 @pytest.mark.slow
 def test_full_c5a_forward_16bit(gjp, oracle_mod):
     _full_config_check(gjp, oracle_mod, "c5a", 2000, dtypes=("bf16", "f16"))

@@ -31,6 +31,7 @@ class WorkloadConfig:
     phantom_seed: int = 0
     n_ellipsoids: int = 12
     note: str = ""
+    clip_cylinder: bool = False  # sample range clipped to the inscribed cylinder
 
     def phantom_ellipsoids(self):
         from .phantoms import random_ellipsoids, sl_stand_in
@@ -57,6 +58,16 @@ CONFIGS = {
                          beam="cone", sod=256.0, sdd=512.0, pitch_u=2.0, pitch_v=2.0,
                          phantom="sl", note="plain FP32 forward; oracle-sized"),
     "c2": _cone("c2", 256, 360, 384, "random", 2, "FP32 forward + adjoint; dot test"),
+    # The paper's speed geometry (Sec. IV-C, Table I): 512^3 box, sample range
+    # clipped to the inscribed cylinder, 512^2 detector, 10 degree cone (the
+    # detector half-width subtends 5 degrees: SOD = 256 / tan 5deg voxels at
+    # magnification 2 with pitch 2, i.e. one voxel per pixel at the axis),
+    # 360 views, FP32.
+    "t1": WorkloadConfig(name="t1", shape=(512, 512, 512), n_views=360, n_u=512, n_v=512,
+                         beam="cone", sod=256.0 / math.tan(math.radians(5.0)),
+                         sdd=2.0 * 256.0 / math.tan(math.radians(5.0)), pitch_u=2.0,
+                         pitch_v=2.0, phantom="sl", clip_cylinder=True,
+                         note="paper's projection-speed geometry"),
     "c3": _cone("c3", 512, 720, 768, "sl", 0, "differentiable projector, 20 GD steps"),
     "c5a": _cone("c5a", 1024, 1440, 1536, "random", 5, "BF16/FP16 storage"),
     "c5b": WorkloadConfig(name="c5b", shape=(2048, 2048, 2048), n_views=64, n_u=3072, n_v=3072,
