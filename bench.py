@@ -151,6 +151,63 @@ def bench_batched(args, torch, gjp, workloads, dev):
     print(json.dumps(out), flush=True)
 
 
+# The paper's GJP_lin FP32 forward with the volume in global memory (Table I,
+# Sec. IV-C geometry): ms per projection on its two GPUs.
+PAPER_T1_MS = {"GTX 1080": 2.70, "GTX 970": 5.69}
+
+
+def bench_t1(args, torch, gjp, workloads, dev):
+    """The paper's projection-speed geometry: 512^3 box clipped to the inscribed
+    cylinder, 512^2 detector, 10 degree cone, 360 views; a step is one FP32
+    forward of all views (Table I reports the time per projection)."""
+    cfg = workloads.config("t1")
+    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    G = gjp.Geometry.from_config(cfg)
+    S = G.count_samples()
+    out_t = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
+    if not args.no_autotune:
+        log(f"autotune float32: tile_v = {gjp.autotune(x, G, out_t)}")
+    for _ in range(max(args.warmup, 1)):
+        gjp.forward(x, G, out_t)
+    torch.cuda.synchronize()
+    gjp.timing_reset()
+    gjp.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gjp.forward(x, G, out_t)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gjp.timing_enable(False)
+    f_ms, f_n = gjp.timing_read("forward")
+    avg = f_ms / max(f_n, 1)
+    ms_proj = 1e3 * elapsed / args.steps / cfg.n_views
+    alg = 16.0 * S + 4.0 * cfg.n_rays
+    achieved = alg / (avg * 1e-3) / 1e9
+    out = {
+        "metric": "GJP_lin FP32 forward, ms per projection (Table I geometry)",
+        "value": ms_proj,
+        "unit": "ms/projection",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": ms_proj / PAPER_T1_MS["GTX 1080"],
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "t1: 512^3 box clipped to the inscribed cylinder, 512^2 "
+                               "detector, 10 degree cone, 360 views; step = one FP32 forward",
+                   "ray_samples_per_pass": S, "rays_per_pass": cfg.n_rays,
+                   "ray_samples_per_s": S / (elapsed / args.steps),
+                   "paper_ms_per_projection": PAPER_T1_MS},
+        "roofline": {"kernel": "forward_f32", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("t1", "forward_f32")},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,6 +237,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "c4":
         return bench_batched(args, torch, gjp, workloads, dev)
+    if args.workload == "t1":
+        return bench_t1(args, torch, gjp, workloads, dev)
     cfg = workloads.config(args.workload)
     log(f"workload {cfg.name}: {cfg.shape} grid, {cfg.n_views} views, {cfg.n_u}x{cfg.n_v}")
     t0 = time.perf_counter()
