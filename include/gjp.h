@@ -164,11 +164,29 @@ gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_
    gives bitwise identical sinograms. Host-only. Errors: GJP_EINVAL. */
 gjp_status gjp_set_forward_tile(const gjp_geometry *g, int32_t vol_dtype, int32_t tile_v);
 
+/* SART (the reconstruction of Sec. IV-B, after Andersen and Kak): the two
+   elementwise steps of one subset update
+       x <- x + lam * A_S^T( (b_S - A_S x) / (A_S 1) ) / (A_S^T 1),
+   the projections A_S and A_S^T being gjp_forward_project / gjp_back_project
+   on a geometry holding the subset's views. A zero row sum (A_S 1) or column
+   sum (A_S^T 1) makes its term zero. All pointers are device float arrays of
+   n elements; queued on `stream`; no synchronisation.
+
+   gjp_sart_residual: out[i] = row_sum[i] > 0 ? (b[i] - ax[i]) / row_sum[i] : 0.
+   `out` may alias `ax`. */
+gjp_status gjp_sart_residual(int64_t n, const float *d_b, const float *d_ax,
+                             const float *d_row_sum, float *d_out, void *stream);
+
+/* gjp_sart_update: x[j] += col_sum[j] > 0 ? lam * bp[j] / col_sum[j] : 0, then
+   x[j] = max(x[j], 0) if nonneg != 0. bp = A_S^T of the residual. */
+gjp_status gjp_sart_update(int64_t n, float *d_x, const float *d_bp, const float *d_col_sum,
+                           float lam, int32_t nonneg, void *stream);
+
 /* Per-kernel GPU timing for benchmarks. While enabled, each launch of the
    library's main kernels is bracketed by HIP events on its stream.
    gjp_timing_read waits for those events and returns the total time in
    milliseconds and the number of launches recorded for `kernel` ("forward",
-   "pad", "adjoint_table", "adjoint_gather", "batched"). */
+   "pad", "adjoint_table", "adjoint_gather", "batched", "sart"). */
 gjp_status gjp_timing_enable(int32_t on);
 gjp_status gjp_timing_reset(void);
 gjp_status gjp_timing_read(const char *kernel, double *total_ms, int64_t *launches);

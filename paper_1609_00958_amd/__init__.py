@@ -11,12 +11,13 @@ from .projector import (Geometry, autotune, back, forward, forward_batched,  # n
                         project, set_forward_tile, timing_enable, timing_read, timing_reset,
                         views_circular_cone,
                         views_parallel)
+from .sart import SART, sart  # noqa: F401
 
 lib()  # load the HIP library now: there is no fallback path
 
 __all__ = [
     "Geometry", "forward", "back", "forward_batched", "project", "autotune",
     "views_circular_cone", "views_parallel", "set_forward_tile", "timing_enable", "timing_read",
-    "timing_reset",
+    "timing_reset", "SART", "sart",
     "GJPError",
 ]

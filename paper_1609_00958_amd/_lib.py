@@ -24,7 +24,7 @@ EXPORTS = (
     "gjp_forward_project_batched", "gjp_views_circular_cone", "gjp_views_parallel",
     "gjp_count_samples", "gjp_autotune_forward", "gjp_set_forward_tile", "gjp_timing_enable",
     "gjp_timing_reset",
-    "gjp_timing_read", "gjp_last_error",
+    "gjp_timing_read", "gjp_last_error", "gjp_sart_residual", "gjp_sart_update",
 )
 
 
@@ -79,6 +79,8 @@ def lib():
     L.gjp_timing_enable.argtypes = [i32]
     L.gjp_timing_reset.argtypes = []
     L.gjp_timing_read.argtypes = [ctypes.c_char_p, f64p, ctypes.POINTER(i64)]
+    L.gjp_sart_residual.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.gjp_sart_update.argtypes = [i64, vp, vp, vp, ctypes.c_float, i32, vp]
     L.gjp_last_error.argtypes = []
     L.gjp_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

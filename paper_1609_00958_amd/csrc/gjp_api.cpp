@@ -8,6 +8,8 @@
 // device queue, HIP graph).
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <cmath>
 #include <stdint.h>
 #include <string.h>
 
@@ -437,6 +439,26 @@ int gjp::geometry_device(const gjp_geometry* g, const double** views, const floa
 // ---------------------------------------------------------------------------
 // sample count (host, same double-precision setup as the kernels)
 // ---------------------------------------------------------------------------
+extern "C" gjp_status gjp_sart_residual(int64_t n, const float* d_b, const float* d_ax,
+                                        const float* d_row_sum, float* d_out, void* stream) {
+  if (n < 0) return fail(GJP_EINVAL, "sart_residual: negative size");
+  if (n > 0 && (!d_b || !d_ax || !d_row_sum || !d_out))
+    return fail(GJP_EINVAL, "sart_residual: null device pointer");
+  return (gjp_status)gjp::launch_sart_residual(n, d_b, d_ax, d_row_sum, d_out,
+                                               (hipStream_t)stream);
+}
+
+extern "C" gjp_status gjp_sart_update(int64_t n, float* d_x, const float* d_bp,
+                                      const float* d_col_sum, float lam, int32_t nonneg,
+                                      void* stream) {
+  if (n < 0) return fail(GJP_EINVAL, "sart_update: negative size");
+  if (n > 0 && (!d_x || !d_bp || !d_col_sum))
+    return fail(GJP_EINVAL, "sart_update: null device pointer");
+  if (!std::isfinite(lam)) return fail(GJP_EINVAL, "sart_update: non-finite relaxation");
+  return (gjp_status)gjp::launch_sart_update(n, d_x, d_bp, d_col_sum, lam, nonneg ? 1 : 0,
+                                             (hipStream_t)stream);
+}
+
 extern "C" gjp_status gjp_count_samples(const gjp_geometry* g, uint64_t* out) {
   if (!g || !out) return fail(GJP_EINVAL, "gjp_count_samples: null pointer");
   const long long n_rays = (long long)g->n_views * g->n_u * g->n_v;

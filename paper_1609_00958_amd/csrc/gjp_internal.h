@@ -86,6 +86,10 @@ int geometry_device(const gjp_geometry* g, const double** views, const float** p
 int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int n[3],
                hipStream_t s);
 int launch_zero_ints(int* p, int n, hipStream_t s);
+int launch_sart_residual(long long n, const float* b, const float* ax, const float* w,
+                         float* out, hipStream_t s);
+int launch_sart_update(long long n, float* x, const float* bp, const float* c, float lam,
+                       int nonneg, hipStream_t s);
 int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,
                    hipStream_t s);
 int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,

@@ -1003,6 +1003,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void b
 }
 
 // ---------------------------------------------------------------------------
+// SART elementwise steps (subset update of the Sec. IV-B reconstruction).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void sart_residual_kernel(long long n,
+                                                            const float* __restrict__ b,
+                                                            const float* ax,
+                                                            const float* __restrict__ w,
+                                                            float* out) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256) {
+    const float wi = w[i];
+    out[i] = wi > 0.0f ? (b[i] - ax[i]) / wi : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(256) void sart_update_kernel(long long n, float* __restrict__ x,
+                                                          const float* __restrict__ bp,
+                                                          const float* __restrict__ c,
+                                                          float lam, int nonneg) {
+  for (long long j = (long long)blockIdx.x * 256 + threadIdx.x; j < n;
+       j += (long long)gridDim.x * 256) {
+    const float cj = c[j];
+    float v = x[j];
+    if (cj > 0.0f) v += lam * bp[j] / cj;
+    if (nonneg) v = fmaxf(v, 0.0f);
+    x[j] = v;
+  }
+}
+
+static int check_launch(const char* what);
+
+static unsigned elementwise_grid(long long n) {
+  const long long blocks = (n + 255) / 256;
+  return (unsigned)(blocks < 8192 ? (blocks < 1 ? 1 : blocks) : 8192);
+}
+
+int launch_sart_residual(long long n, const float* b, const float* ax, const float* w,
+                         float* out, hipStream_t s) {
+  if (n <= 0) return 0;
+  TimedLaunch t = timing_begin("sart", s);
+  sart_residual_kernel<<<elementwise_grid(n), 256, 0, s>>>(n, b, ax, w, out);
+  timing_end("sart", t, s);
+  return check_launch("sart residual kernel");
+}
+
+int launch_sart_update(long long n, float* x, const float* bp, const float* c, float lam,
+                       int nonneg, hipStream_t s) {
+  if (n <= 0) return 0;
+  TimedLaunch t = timing_begin("sart", s);
+  sart_update_kernel<<<elementwise_grid(n), 256, 0, s>>>(n, x, bp, c, lam, nonneg);
+  timing_end("sart", t, s);
+  return check_launch("sart update kernel");
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static int check_launch(const char* what) {
