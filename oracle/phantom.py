@@ -14,12 +14,13 @@ from __future__ import annotations
 import numpy as np
 
 
-def ray_lines(g, rays: np.ndarray):
-    """World-space (point, direction) of each ray (view, iu, iv)."""
+def ray_lines(g, rays: np.ndarray, offsets=(0.0, 0.0)):
+    """World-space (point, direction) of each ray (view, iu, iv); `offsets`
+    shifts the detector point by a fraction of a pixel along u and v."""
     rays = np.asarray(rays, dtype=np.int64).reshape(-1, 3)
     V = g.views[rays[:, 0]]
-    iu = rays[:, 1:2].astype(np.float64)
-    iv = rays[:, 2:3].astype(np.float64)
+    iu = rays[:, 1:2].astype(np.float64) + offsets[0]
+    iv = rays[:, 2:3].astype(np.float64) + offsets[1]
     d = V[:, 3:6] + iu * V[:, 6:9] + iv * V[:, 9:12]
     if g.beam == 0:
         a = V[:, 0:3]
@@ -54,8 +55,9 @@ def box_interval(g, a: np.ndarray, u: np.ndarray):
     return t0, t1
 
 
-def line_integrals(ellipsoids, g, rays: np.ndarray, clip: bool = True) -> np.ndarray:
-    a, u = ray_lines(g, rays)
+def line_integrals(ellipsoids, g, rays: np.ndarray, clip: bool = True,
+                   offsets=(0.0, 0.0)) -> np.ndarray:
+    a, u = ray_lines(g, rays, offsets)
     ulen = np.linalg.norm(u, axis=1)
     if clip:
         tb0, tb1 = box_interval(g, a, u)
@@ -79,3 +81,14 @@ def line_integrals(ellipsoids, g, rays: np.ndarray, clip: bool = True) -> np.nda
         seg = np.where(hit, np.maximum(t2 - t1, 0.0), 0.0)
         out += e.density * seg * ulen
     return out
+
+
+def pixel_integrals(ellipsoids, g, rays: np.ndarray, n_sub: int = 8, clip: bool = True):
+    """Mean of the line integrals over n_sub x n_sub regularly spaced points of
+    each detector pixel (Sec. IV-A averages 8 x 8 rays per pixel)."""
+    offs = [((j + 0.5) / n_sub - 0.5) for j in range(n_sub)]
+    acc = np.zeros(np.asarray(rays).reshape(-1, 3).shape[0])
+    for ou in offs:
+        for ov in offs:
+            acc += line_integrals(ellipsoids, g, rays, clip=clip, offsets=(ou, ov))
+    return acc / float(n_sub * n_sub)

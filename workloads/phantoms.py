@@ -95,48 +95,69 @@ def _axis_coords(shape, voxel_size, center):
 
 def rasterize(ellipsoids: Sequence[Ellipsoid], shape: Sequence[int],
               voxel_size=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0),
-              dtype=np.float32) -> np.ndarray:
-    """Point-sample the phantom at voxel centres (FP64 inside test), C order."""
+              dtype=np.float32, supersample: int = 1) -> np.ndarray:
+    """Point-sample the phantom at voxel centres (FP64 inside test), C order.
+    With supersample = k each voxel is the mean over k^3 regularly spaced
+    points at offsets ((j + 0.5) / k - 0.5) voxel per axis (Sec. IV-A uses
+    k = 5)."""
     shape = tuple(int(s) for s in shape)
-    xs, ys, zs = _axis_coords(shape, voxel_size, center)
+    k = int(supersample)
+    offs = [((j + 0.5) / k - 0.5) for j in range(k)]
     vol = np.zeros(shape, dtype=np.float64)
-    Y, Z = np.meshgrid(ys, zs, indexing="ij")
-    for e in ellipsoids:
-        R = e.rot()
-        inv_a = 1.0 / np.asarray(e.semi_axes, dtype=np.float64)
-        cx, cy, cz = e.center
-        for i0, x in enumerate(xs):
-            dx, dy, dz = x - cx, Y - cy, Z - cz
-            q = np.zeros_like(Y)
-            for j in range(3):
-                loc = R[0, j] * dx + R[1, j] * dy + R[2, j] * dz
-                q += (loc * inv_a[j]) ** 2
-            vol[i0] += np.where(q <= 1.0, e.density, 0.0)
-    return vol.astype(dtype)
+    for o0 in offs:
+        for o1 in offs:
+            for o2 in offs:
+                xs, ys, zs = _axis_coords(shape, voxel_size, center)
+                xs = xs + o0 * voxel_size[0]
+                ys = ys + o1 * voxel_size[1]
+                zs = zs + o2 * voxel_size[2]
+                Y, Z = np.meshgrid(ys, zs, indexing="ij")
+                for e in ellipsoids:
+                    R = e.rot()
+                    inv_a = 1.0 / np.asarray(e.semi_axes, dtype=np.float64)
+                    cx, cy, cz = e.center
+                    for i0, x in enumerate(xs):
+                        dx, dy, dz = x - cx, Y - cy, Z - cz
+                        q = np.zeros_like(Y)
+                        for j in range(3):
+                            loc = R[0, j] * dx + R[1, j] * dy + R[2, j] * dz
+                            q += (loc * inv_a[j]) ** 2
+                        vol[i0] += np.where(q <= 1.0, e.density, 0.0)
+    return (vol / float(k ** 3)).astype(dtype)
 
 
 def rasterize_torch(ellipsoids: Sequence[Ellipsoid], shape: Sequence[int], device,
-                    voxel_size=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0), dtype=None):
-    """Same point sampling as `rasterize`, evaluated with torch in FP64 one
-    x-slab at a time (for grids too large for numpy on the host)."""
+                    voxel_size=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0), dtype=None,
+                    supersample: int = 1):
+    """Same point sampling as `rasterize` (including `supersample`), evaluated
+    with torch in FP64 one x-slab at a time (for grids too large for numpy on
+    the host)."""
     import torch
     dtype = dtype or torch.float32
     shape = tuple(int(s) for s in shape)
-    xs, ys, zs = [torch.as_tensor(a, dtype=torch.float64, device=device)
-                  for a in _axis_coords(shape, voxel_size, center)]
+    k = int(supersample)
+    offs = torch.tensor([((j + 0.5) / k - 0.5) for j in range(k)], dtype=torch.float64,
+                        device=device)
+    base = [torch.as_tensor(a, dtype=torch.float64, device=device)
+            for a in _axis_coords(shape, voxel_size, center)]
+    # sub-sample coordinates of one slab: (k, n1, 1) along y and (k, 1, n2) along z,
+    # combined by broadcasting into (k, k, n1, n2)
+    ys = (base[1][None, :] + offs[:, None] * voxel_size[1])[:, None, :, None]
+    zs = (base[2][None, :] + offs[:, None] * voxel_size[2])[None, :, None, :]
     vol = torch.empty(shape, dtype=dtype, device=device)
-    Y, Z = torch.meshgrid(ys, zs, indexing="ij")
     ells = [(torch.as_tensor(e.rot(), dtype=torch.float64, device=device),
              [1.0 / a for a in e.semi_axes], e.center, e.density) for e in ellipsoids]
     for i0 in range(shape[0]):
-        x = xs[i0]
-        acc = torch.zeros_like(Y)
-        for R, inv_a, (cx, cy, cz), rho in ells:
-            dx, dy, dz = x - cx, Y - cy, Z - cz
-            q = torch.zeros_like(Y)
-            for j in range(3):
-                loc = R[0, j] * dx + R[1, j] * dy + R[2, j] * dz
-                q += (loc * inv_a[j]) ** 2
-            acc += torch.where(q <= 1.0, rho, 0.0)
-        vol[i0] = acc.to(dtype)
+        acc = torch.zeros((shape[1], shape[2]), dtype=torch.float64, device=device)
+        for o0 in range(k):
+            x = base[0][i0] + offs[o0] * voxel_size[0]
+            for R, inv_a, (cx, cy, cz), rho in ells:
+                dx, dy, dz = x - cx, ys - cy, zs - cz
+                q = None
+                for j in range(3):
+                    loc = R[0, j] * dx + R[1, j] * dy + R[2, j] * dz
+                    t = (loc * inv_a[j]) ** 2
+                    q = t if q is None else q + t
+                acc += torch.where(q <= 1.0, rho, 0.0).sum(dim=(0, 1))
+        vol[i0] = (acc / float(k ** 3)).to(dtype)
     return vol
