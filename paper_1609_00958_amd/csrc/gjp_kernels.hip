@@ -251,8 +251,8 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// One plane of the row-uniform loop. q = {row byte offset, wfa, wca} of the
-// plane (wave-uniform); CHECK zeroes the axis-2 weights of lanes whose sample
+// One plane of the row-uniform loop. q = {row byte offset, wfa, wca, plane
+// index as a float} of the plane (wave-uniform); CHECK zeroes the axis-2 weights of lanes whose sample
 // range excludes the plane (the load stays in bounds: the row is inside the
 // copy and the axis-2 coordinate is clamped). A zeroed plane adds +-0, so the
 // lane's sum is unchanged.
@@ -262,7 +262,7 @@ __device__ __forceinline__ void ru_plane(__amdgpu_buffer_rsrc_t rs, const float4
   constexpr uint32_t pe = 2 * sizeof(T);
   int ib;
   float wfb, wcb;
-  sample_axis<WF>((float)i, R.gb, R.cb, hib, ib, wfb, wcb);
+  sample_axis<WF>(q.w, R.gb, R.cb, hib, ib, wfb, wcb);
   if (CHECK) {
     const bool in = i >= R.i0 && i < R.i1;
     wfb = in ? wfb : 0.0f;
@@ -312,7 +312,7 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
         (int)(uint32_t)min(a.copy_bytes - org, 0xffffffffull), 0x00020000);
     const uint32_t row_l = (uint32_t)((unsigned long long)lane * Sm +
                                       (unsigned long long)(ia_l - ia_min) * Sa);
-    slots[lane] = make_float4(__uint_as_float(row_l), wfa_l, wca_l, 0.0f);
+    slots[lane] = make_float4(__uint_as_float(row_l), wfa_l, wca_l, (float)(base + lane));
     __builtin_amdgcn_wave_barrier();
     const int cnt = min(64, hi - base);
     const int j0 = min(max(mid_lo - base, 0), cnt);
@@ -322,11 +322,10 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
     // two planes per iteration: both wide loads are issued first
     for (; j + 1 < j1; j += 2) {
       const float4 q0 = slots[j], q1 = slots[j + 1];
-      const int i = base + j;
       int ib0, ib1;
       float wfb0, wcb0, wfb1, wcb1;
-      sample_axis<WF>((float)i, R.gb, R.cb, hib, ib0, wfb0, wcb0);
-      sample_axis<WF>((float)(i + 1), R.gb, R.cb, hib, ib1, wfb1, wcb1);
+      sample_axis<WF>(q0.w, R.gb, R.cb, hib, ib0, wfb0, wcb0);
+      sample_axis<WF>(q1.w, R.gb, R.cb, hib, ib1, wfb1, wcb1);
       const uint32_t vo0 = (uint32_t)(ib0 + 1) * pe + __float_as_uint(q0.x);
       const uint32_t vo1 = (uint32_t)(ib1 + 1) * pe + __float_as_uint(q1.x);
       const Quad u0 = buf_quad(rs, vo0, 0, (const T*)nullptr);
@@ -687,9 +686,9 @@ __global__ __launch_bounds__(256) void adj_splat_kernel(
 
 // Weights of one sample for the voxels z and z + 1 (zero unless the sample's
 // floor or floor + 1 is one of them). Linear: the tent 1 - |p - z| on the
-// clamped coordinate, which reproduces the forward's 1 - d and 1 - (1 - d)
-// (exact differences of nearby floats); other weights: the forward's floor
-// and complementary weights, selected by the floor's position.
+// clamped coordinate, which reproduces the forward's 1 - d and d (differences
+// of nearby floats are exact); other weights: the forward's floor and
+// complementary weights, selected by the floor's position.
 template <int WF>
 __device__ __forceinline__ void pair_weights(float fplane, float g, float c, float hz, float fz,
                                              int z, float& b0, float& b1) {
@@ -698,8 +697,9 @@ __device__ __forceinline__ void pair_weights(float fplane, float g, float c, flo
     p = __builtin_amdgcn_fmed3f(p, -1.0f, hz);
     const float s0 = p - fz;
     const float s1 = s0 - 1.0f;
-    b0 = __builtin_fmaxf(1.0f - __builtin_fabsf(s0), 0.0f);
-    b1 = __builtin_fmaxf(1.0f - __builtin_fabsf(s1), 0.0f);
+    // clamp to [0, 1] (one instruction with the clamp modifier); 1 - |s| <= 1
+    b0 = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(s0), 0.0f, 1.0f);
+    b1 = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(s1), 0.0f, 1.0f);
   } else {
     int ib;
     float wfb, wcb;

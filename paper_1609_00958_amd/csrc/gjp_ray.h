@@ -241,7 +241,11 @@ __device__ __forceinline__ void sample_axis(float fi, float g, float c, float hi
   const float f = __builtin_floorf(p);
   const float d = p - f;
   w_fl = weight_fn<WF>(d);
-  w_cl = 1.0f - w_fl;
+  // complementary weight (Eq. 12); for the linear weight 1 - (1 - d) is d
+  if constexpr (WF == W_LINEAR)
+    w_cl = d;
+  else
+    w_cl = 1.0f - w_fl;
   i_fl = (int)f;
 }
 
