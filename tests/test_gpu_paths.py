@@ -18,7 +18,8 @@ def gjp():
 def _oracle_geom(oracle_mod, G):
     beam = oracle_mod.CONE if G.beam == 0 else oracle_mod.PARALLEL
     return oracle_mod.Geometry(G.shape, G.views, G.n_u, G.n_v, beam=beam,
-                               voxel_size=G.voxel_size, center=G.center, weight=G.weight)
+                               voxel_size=G.voxel_size, center=G.center, weight=G.weight,
+                               clip_cylinder=G.clip_cylinder)
 
 
 # ---------------------------------------------------------------------------
@@ -54,6 +55,31 @@ def test_batched_equals_single_launches(gjp):
         for v, G, o in zip(vols, geoms, outs):
             ref = gjp.forward(v, G)
             assert torch.equal(o, ref)
+
+
+def test_batched_with_cylinder_clipping(gjp, oracle_mod):
+    """Clipped and unclipped instances in one batched launch: each equals its
+    single-instance forward bitwise and the oracle within the FP32 bound."""
+    import torch
+    dev = cuda()
+    geoms = []
+    for k, cfg in enumerate((
+            workloads.WorkloadConfig("a", (40, 36, 30), 12, 50, 33, beam="cone", sod=150.0,
+                                     sdd=300.0, pitch_u=1.7, pitch_v=1.7, clip_cylinder=True),
+            workloads.WorkloadConfig("b", (33, 33, 20), 9, 44, 21, beam="parallel",
+                                     clip_cylinder=True),
+            workloads.WorkloadConfig("c", (28, 31, 25), 7, 40, 30, beam="cone", sod=120.0,
+                                     sdd=240.0, pitch_u=1.6, pitch_v=1.6))):
+        geoms.append(gjp.Geometry.from_config(cfg, weight="spline" if k == 1 else "linear"))
+    gen = torch.Generator().manual_seed(310)
+    vols = [torch.rand(G.shape, generator=gen).to(dev) for G in geoms]
+    note("batched clipped")
+    outs = gjp.forward_batched(vols, geoms)
+    torch.cuda.synchronize()
+    for v, G, o in zip(vols, geoms, outs):
+        assert torch.equal(o, gjp.forward(v, G))
+        want = oracle_mod.forward(_oracle_geom(oracle_mod, G), v.cpu().numpy())
+        assert rel_l2(o.cpu().numpy(), want) <= 1e-5
 
 
 def test_batched_matches_oracle(gjp, oracle_mod):

@@ -55,6 +55,23 @@ def test_sart_matches_oracle(gjp, oracle_mod, n_subsets, lam, nonneg, n_iter, cl
         assert x.min() >= 0.0
 
 
+def test_sart_parallel_beam(gjp, oracle_mod):
+    import torch
+    from oracle import sart as osart
+    dev = cuda()
+    shape = (24, 24, 12)
+    cfg = workloads.WorkloadConfig("p", shape, 18, 30, 14, beam="parallel", pitch_u=0.9,
+                                   pitch_v=1.0)
+    og = oracle_mod.geometry_for(cfg)
+    x_true = workloads.rasterize(workloads.random_ellipsoids(96, shape), shape)
+    b = oracle_mod.forward(og, x_true).astype(np.float32)
+    G = gjp.Geometry.from_config(cfg)
+    note("sart parallel")
+    x = gjp.sart(G, torch.from_numpy(b).to(dev), 2, 6, lam=0.8).cpu().numpy()
+    want = osart.sart_projector(og, b.astype(np.float64), 2, 6, lam=0.8)
+    assert rel_l2(x, want) <= TOL_SART
+
+
 def test_sart_reduces_residual(gjp, oracle_mod):
     import torch
     dev = cuda()
