@@ -144,15 +144,20 @@ __device__ __forceinline__ E padded_value(const E* __restrict__ src, int n0, int
   return (E)0;
 }
 
+// One pair element of each copy, written as one 2-element store.
 template <typename E>
 __device__ __forceinline__ void pad_pair_element(const E* __restrict__ src, E* __restrict__ A,
                                                  E* __restrict__ B, int n0, int n1, int n2,
                                                  long long e, int x, int y, int z) {
+  typedef E E2 __attribute__((ext_vector_type(2)));
   const E v = padded_value(src, n0, n1, n2, x, y, z);
-  A[2 * e] = v;
-  A[2 * e + 1] = padded_value(src, n0, n1, n2, x, y + 1, z);
-  B[2 * e] = v;
-  B[2 * e + 1] = padded_value(src, n0, n1, n2, x + 1, y, z);
+  E2 pa, pb;
+  pa.x = v;
+  pa.y = padded_value(src, n0, n1, n2, x, y + 1, z);
+  pb.x = v;
+  pb.y = padded_value(src, n0, n1, n2, x + 1, y, z);
+  reinterpret_cast<E2*>(A)[e] = pa;
+  reinterpret_cast<E2*>(B)[e] = pb;
 }
 
 template <typename E>
