@@ -43,6 +43,26 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def measured_copy_gbs(torch, dev):
+    """Device-to-device copy rate of a 2 GiB buffer (bytes read + written per
+    second), a measured stream peak to set beside the nominal HBM figure."""
+    src = torch.empty(1 << 29, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    gbs = 2.0 * src.numel() * 4 / (ms * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch (fetch + write) of `kernel` from the committed rocprofv3
     summary of this workload, or None if there is none or the kernel sources
@@ -364,8 +384,10 @@ def main():
     gat_avg = gat_ms / max(gat_n, 1)
     adj_launches_per_step = max(gat_n // args.steps, 1)
     adj_ms_step = (gat_ms + tab_ms) / args.steps
-    # algorithmic bytes of one gather launch: 16 B per sample of its view chunk + 4 B per voxel
-    gat_bytes = (16.0 * S + 4.0 * n_vox * adj_launches_per_step) / adj_launches_per_step
+    # algorithmic bytes of one gather launch: 16 B per sample of its view chunk, 4 B per
+    # ray of the chunk read and 4 B per voxel written
+    gat_bytes = (16.0 * S + 4.0 * n_rays + 4.0 * n_vox * adj_launches_per_step) / \
+        adj_launches_per_step
     kernels = {
         "forward_f32": per_dtype["f32"],
         "forward_bf16": per_dtype["bf16"],
@@ -388,6 +410,9 @@ def main():
     else:
         dom = "forward_f32"
         achieved = per_dtype["f32"]["alg_GBps"]
+    # a profiled run (--calibrate-copy) keeps its 1 GiB copy the largest copy
+    # dispatch, which the byte-counter scaling takes as its reference
+    copy_gbs = None if args.calibrate_copy else measured_copy_gbs(torch, dev)
     roofline = {
         "kernel": dom,
         "bound": "hbm",
@@ -395,6 +420,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
+        "measured_copy_GBps": copy_gbs,
+        "frac_of_measured_copy": achieved / copy_gbs if copy_gbs else None,
         "traffic": measured_traffic(args.workload, "adjoint_gather" if dom == "adjoint_gather"
                                     else "forward_f32"),
     }
