@@ -107,13 +107,22 @@ def cpu_baseline(cfg, vol_np, target_s: float):
     _, c = oracle.forward_rays(og, vol_np, rays, with_counts=True)
     dt = time.perf_counter() - t0
     samples = int(c.sum())
+    # the same oracle on one thread, over a slice of the sample sized for a few seconds
+    n1 = int(min(n_rays, max(1000, 3.0 * samples / dt / cores / max(c.mean(), 1.0))))
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    _, c1 = oracle.forward_rays(og, vol_np, rays[:n1], with_counts=True)
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
     return {
         "value": samples / dt,
         "unit": "ray-samples/s",
         "cores": cores,
         "kind": "oracle",
+        "value_1core": int(c1.sum()) / dt1,
         "sample": f"FP64 oracle forward of {n_rays} uniformly sampled rays of the workload "
-                  f"({samples} ray-samples, {dt:.1f} s, {cpu_model()})",
+                  f"({samples} ray-samples, {dt:.1f} s, {cpu_model()}); value_1core: the "
+                  f"first {n1} of those rays on one thread ({dt1:.1f} s)",
     }
 
 
@@ -379,6 +388,24 @@ def main():
             "ray_samples_per_s": S / (avg * 1e-3),
             "alg_GBps": (bps * S + 4 * G.n_views * G.n_u * G.n_v) / (avg * 1e-3) / 1e9,
         }
+    # the plain one-lane-per-ray kernel on the same volumes, for context
+    naive = {}
+    for name, v, bps in (("f32", x, 16), ("bf16", x_bf16, 8)):
+        gjp.forward_naive(v, G)
+        torch.cuda.synchronize()
+        gjp.timing_reset()
+        gjp.timing_enable(True)
+        for _ in range(2):
+            gjp.forward_naive(v, G)
+        torch.cuda.synchronize()
+        gjp.timing_enable(False)
+        ms, n = gjp.timing_read("forward_naive")
+        avg = ms / max(n, 1)
+        naive[name] = {
+            "ms": avg,
+            "ray_samples_per_s": S / (avg * 1e-3),
+            "alg_GBps": (bps * S + 4 * G.n_views * G.n_u * G.n_v) / (avg * 1e-3) / 1e9,
+        }
     n_rays = G.n_views * G.n_u * G.n_v
     n_vox = int(np.prod(cfg.shape))
     gat_avg = gat_ms / max(gat_n, 1)
@@ -401,6 +428,10 @@ def main():
         },
         "speedup_bf16_vs_f32": per_dtype["f32"]["ms"] / per_dtype["bf16"]["ms"],
         "speedup_f16_vs_f32": per_dtype["f32"]["ms"] / per_dtype["f16"]["ms"],
+        "forward_naive_f32": naive["f32"],
+        "forward_naive_bf16": naive["bf16"],
+        "speedup_f32_vs_naive_f32": naive["f32"]["ms"] / per_dtype["f32"]["ms"],
+        "speedup_bf16_vs_naive_f32": naive["f32"]["ms"] / per_dtype["bf16"]["ms"],
     }
     # dominant kernel of the step
     fwd_step_ms = fwd_ms / args.steps

@@ -104,6 +104,16 @@ gjp_status gjp_destroy_geometry(gjp_geometry *g);
 gjp_status gjp_forward_project(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
                                float *d_sino, void *stream);
 
+/* Plain forward projection for comparison (Algorithm 1 as written: one lane
+   per ray, the four neighbours of each sample read from d_vol itself with a
+   zero-padding bounds test each, Eq. 8). Arguments and layouts as for
+   gjp_forward_project; the ray setup, weights and summation order are the
+   same, without its padded copies, ray tiles or launch ordering. Allocates
+   nothing. Errors: GJP_EINVAL (null pointer, unknown dtype),
+   GJP_EUNSUPPORTED (more than 2^40 rays), GJP_EHIP. */
+gjp_status gjp_forward_project_naive(const gjp_geometry *g, const void *d_vol,
+                                     int32_t vol_dtype, float *d_sino, void *stream);
+
 /* Adjoint (exact transpose) x = A^T y of gjp_forward_project for the same
    geometry: every sample's single-precision weights are recomputed exactly as
    the forward computes them. When every view's dv is parallel to axis 2 and no
@@ -186,7 +196,8 @@ gjp_status gjp_sart_update(int64_t n, float *d_x, const float *d_bp, const float
    library's main kernels is bracketed by HIP events on its stream.
    gjp_timing_read waits for those events and returns the total time in
    milliseconds and the number of launches recorded for `kernel` ("forward",
-   "pad", "adjoint_table", "adjoint_gather", "batched", "sart"). */
+   "forward_naive", "pad", "adjoint_table", "adjoint_gather", "batched",
+   "sart"). */
 gjp_status gjp_timing_enable(int32_t on);
 gjp_status gjp_timing_reset(void);
 gjp_status gjp_timing_read(const char *kernel, double *total_ms, int64_t *launches);

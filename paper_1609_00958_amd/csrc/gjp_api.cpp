@@ -638,6 +638,19 @@ extern "C" gjp_status gjp_forward_project(const gjp_geometry* g, const void* d_v
                            tile_for(g, vol_dtype));
 }
 
+extern "C" gjp_status gjp_forward_project_naive(const gjp_geometry* g, const void* d_vol,
+                                                int32_t vol_dtype, float* d_sino, void* stream) {
+  gjp_status st = validate_fwd(g, d_vol, vol_dtype, d_sino);
+  if (st != GJP_OK) return st;
+  const double* d_views = nullptr;
+  const float* d_proj = nullptr;
+  int r = gjp::geometry_device(g, &d_views, &d_proj);
+  if (r != GJP_OK) return (gjp_status)r;
+  return (gjp_status)gjp::launch_forward_naive(g->gg, d_views, d_vol, vol_dtype, g->weight,
+                                               g->n_views, g->n_u, g->n_v, d_sino,
+                                               (hipStream_t)stream);
+}
+
 extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_vol,
                                            int32_t vol_dtype, float* d_sino, void* stream,
                                            int32_t* tile_v_out) {

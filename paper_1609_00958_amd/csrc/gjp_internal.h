@@ -92,6 +92,8 @@ int launch_sart_update(long long n, float* x, const float* bp, const float* c, f
                        int nonneg, hipStream_t s);
 int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,
                    hipStream_t s);
+int launch_forward_naive(const GridGeom& G, const double* views, const void* vol, int dtype,
+                         int weight, int n_views, int n_u, int n_v, float* sino, hipStream_t s);
 int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,
                          int view0, int n_chunk, float4* table, float4* cols, int* mask,
                          hipStream_t s);

@@ -436,6 +436,67 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Plain forward for comparison: one lane per ray in sinogram order (v
+// fastest), the four neighbours of a sample read one by one from the
+// unpadded volume with a bounds test each (zero outside, Eq. 8), no padded
+// copies, tiling, view grouping or shared row setup. Same ray setup, weights
+// and summation order as the tuned kernel.
+__device__ __forceinline__ float widen1(float x) { return x; }
+__device__ __forceinline__ float widen1(bf16_t x) { return __uint_as_float((uint32_t)x.bits << 16); }
+__device__ __forceinline__ float widen1(f16_t x) {
+  return (float)__builtin_bit_cast(_Float16, x.bits);
+}
+
+// Voxel (i, a, b) on the (driving, first, second transverse) axes, zero
+// outside the grid; i is always inside.
+template <typename T>
+__device__ __forceinline__ float voxel_or_zero(const T* __restrict__ vol, long long off, int a,
+                                               int b, int na, int nb, long long sa, long long sb) {
+  if (a < 0 || a >= na || b < 0 || b >= nb) return 0.0f;
+  return widen1(vol[off + a * sa + b * sb]);
+}
+
+template <typename T, int WF>
+__global__ __launch_bounds__(256) void naive_fwd_kernel(const GridGeom G,
+                                                        const double* __restrict__ views,
+                                                        const T* __restrict__ vol, int n_u,
+                                                        int n_v, long long n_rays,
+                                                        float* __restrict__ sino) {
+  const long long ray = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (ray >= n_rays) return;
+  const long long per_view = (long long)n_u * n_v;
+  const int view = (int)(ray / per_view);
+  const int rem = (int)(ray - (long long)view * per_view);
+  const int iu = rem / n_v, iv = rem - (rem / n_v) * n_v;
+  RaySetup R;
+  ray_setup(views + 12 * (size_t)view, G, iu, iv, R);
+  // strides of the C-order volume: axis 0 n1*n2, axis 1 n2, axis 2 1
+  const long long st0 = (long long)G.n[1] * G.n[2], st1 = G.n[2];
+  const long long sm = R.m == 0 ? st0 : (R.m == 1 ? st1 : 1);
+  const long long sa = R.ta == 0 ? st0 : st1;  // ta < tb, so ta is 0 or 1
+  const long long sb = R.tb == 1 ? st1 : 1;    // and tb is 1 or 2
+  const int na = G.n[R.ta == 0 ? 0 : 1], nb = G.n[R.tb == 1 ? 1 : 2];
+  const float hia = G.hi[R.ta == 0 ? 0 : 1], hib = G.hi[R.tb == 1 ? 1 : 2];
+  float acc = 0.0f;
+  float fi = (float)R.i0;
+  for (int i = R.i0; i < R.i1; ++i) {
+    int ia, ib;
+    float wfa, wca, wfb, wcb;
+    sample_axis<WF>(fi, R.ga, R.ca, hia, ia, wfa, wca);
+    sample_axis<WF>(fi, R.gb, R.cb, hib, ib, wfb, wcb);
+    const long long off = (long long)i * sm;
+    Quad q;
+    q.a0z0 = voxel_or_zero(vol, off, ia, ib, na, nb, sa, sb);
+    q.a0z1 = voxel_or_zero(vol, off, ia, ib + 1, na, nb, sa, sb);
+    q.a1z0 = voxel_or_zero(vol, off, ia + 1, ib, na, nb, sa, sb);
+    q.a1z1 = voxel_or_zero(vol, off, ia + 1, ib + 1, na, nb, sa, sb);
+    acc = accumulate4(acc, wfa, wca, wfb, wcb, q);
+    fi += 1.0f;
+  }
+  sino[ray] = acc * R.scale;
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint pass 1: per-ray table for views [view0, view0 + n_chunk).
 // General layout, two float4 per ray: {m | i0 << 2 | i1 << 17, ca, ga, cb},
 // {gb, y * scale, 0, 0}. Column layout (see adj_gather_sep_kernel): one float4
@@ -1115,6 +1176,33 @@ int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_vi
   }
   timing_end("forward", t, s);
   return check_launch("forward kernel");
+}
+
+template <typename T, int WF>
+static void launch_naive_t(const GridGeom& G, const double* views, const void* vol, int n_u,
+                           int n_v, long long n_rays, float* sino, unsigned grid, hipStream_t s) {
+  naive_fwd_kernel<T, WF><<<grid, 256, 0, s>>>(G, views, static_cast<const T*>(vol), n_u, n_v,
+                                                n_rays, sino);
+}
+
+int launch_forward_naive(const GridGeom& G, const double* views, const void* vol, int dtype,
+                         int weight, int n_views, int n_u, int n_v, float* sino, hipStream_t s) {
+  const long long n_rays = (long long)n_views * n_u * n_v;
+  if (n_rays == 0) return 0;
+  const long long nb = (n_rays + 255) / 256;
+  if (nb > 0xffffffffll) return set_error(-4, "naive forward: too many rays for one launch");
+  const unsigned grid = (unsigned)nb;
+  TimedLaunch t = timing_begin("forward_naive", s);
+  switch (dtype * 2 + weight) {
+    case 0: launch_naive_t<float, W_LINEAR>(G, views, vol, n_u, n_v, n_rays, sino, grid, s); break;
+    case 1: launch_naive_t<float, W_SPLINE>(G, views, vol, n_u, n_v, n_rays, sino, grid, s); break;
+    case 2: launch_naive_t<bf16_t, W_LINEAR>(G, views, vol, n_u, n_v, n_rays, sino, grid, s); break;
+    case 3: launch_naive_t<bf16_t, W_SPLINE>(G, views, vol, n_u, n_v, n_rays, sino, grid, s); break;
+    case 4: launch_naive_t<f16_t, W_LINEAR>(G, views, vol, n_u, n_v, n_rays, sino, grid, s); break;
+    default: launch_naive_t<f16_t, W_SPLINE>(G, views, vol, n_u, n_v, n_rays, sino, grid, s); break;
+  }
+  timing_end("forward_naive", t, s);
+  return check_launch("naive forward kernel");
 }
 
 int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,

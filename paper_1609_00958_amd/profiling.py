@@ -24,7 +24,13 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/gjp_kernels.hip", "csrc/gjp_ray.h")
 
+# First match wins: the longer kernel names come before their substrings.
 SHORT = (
+    ("naive_fwd_kernel<float", "forward_naive_f32"),
+    ("naive_fwd_kernel<gjp::bf16_t", "forward_naive_bf16"),
+    ("naive_fwd_kernel<gjp::f16_t", "forward_naive_f16"),
+    ("batched_fwd_kernel", "batched"),
+    ("batched_pad_kernel", "batched_pad"),
     ("fwd_kernel<float", "forward_f32"),
     ("fwd_kernel<gjp::bf16_t", "forward_bf16"),
     ("fwd_kernel<gjp::f16_t", "forward_f16"),
@@ -32,8 +38,6 @@ SHORT = (
     ("adj_splat_kernel", "adjoint_gather"),
     ("adj_table_kernel", "adjoint_table"),
     ("pad_kernel", "pad"),
-    ("batched_fwd_kernel", "batched"),
-    ("batched_pad_kernel", "batched_pad"),
     ("__amd_rocclr_copyBuffer", "copy"),
 )
 

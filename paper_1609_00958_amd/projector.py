@@ -165,6 +165,21 @@ def forward(vol, geom: Geometry, out=None):
     return out
 
 
+def forward_naive(vol, geom: Geometry, out=None):
+    """Sinogram A vol from the plain one-lane-per-ray kernel (for comparison)."""
+    torch = _torch()
+    _check_tensor(vol, geom.shape, "volume")
+    if out is None:
+        out = torch.empty(geom.sino_shape, dtype=torch.float32, device=vol.device)
+    _check_tensor(out, geom.sino_shape, "sinogram")
+    if out.dtype != torch.float32:
+        raise TypeError("sinogram must be float32")
+    with torch.cuda.device(vol.device):
+        check(lib().gjp_forward_project_naive(geom.handle, vol.data_ptr(), _dtype_code(vol),
+                                              out.data_ptr(), _stream(vol.device)))
+    return out
+
+
 def back(sino, geom: Geometry, out=None):
     """Adjoint A^T sino, float32 (n0, n1, n2), on sino's device."""
     torch = _torch()

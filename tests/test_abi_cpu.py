@@ -77,6 +77,9 @@ def test_error_paths_without_gpu(gjp):
     assert L.gjp_forward_project(h, 16, 9, 16, None) == _lib.GJP_EINVAL
     assert L.gjp_forward_project(None, 16, 0, 16, None) == _lib.GJP_EINVAL
     assert L.gjp_forward_project(h, 18, 0, 16, None) == _lib.GJP_EINVAL  # misaligned
+    assert L.gjp_forward_project_naive(h, None, 0, None, None) == _lib.GJP_EINVAL
+    assert L.gjp_forward_project_naive(h, 16, 9, 16, None) == _lib.GJP_EINVAL
+    assert L.gjp_forward_project_naive(None, 16, 0, 16, None) == _lib.GJP_EINVAL
     assert L.gjp_back_project(h, None, 16, None) == _lib.GJP_EINVAL
     assert L.gjp_forward_project_batched(0, None, None, None, None, None) == _lib.GJP_EINVAL
     cnt = ctypes.c_uint64()

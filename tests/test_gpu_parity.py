@@ -322,3 +322,45 @@ def test_cylinder_clipping_circular(gjp, oracle_mod, beam):
     note(f"clip adjoint circular {beam}")
     x = gjp.back(_to_dev(s, dev), G).cpu().numpy()
     assert rel_l2(x, oracle_mod.adjoint(og, s)) <= TOL32
+
+
+# ---------------------------------------------------------------------------
+# plain one-lane-per-ray forward (comparison kernel)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("beam,weight,clip", [("cone", "linear", False),
+                                              ("parallel", "spline", False),
+                                              ("cone", "linear", True)])
+def test_naive_forward_random_geometry(gjp, oracle_mod, beam, weight, clip):
+    """Every driving axis, ragged sizes; against the oracle and the tuned kernel
+    (same setup, weights and summation order, so the two agree to rounding)."""
+    dev = cuda()
+    shape = (33, 27, 52)
+    n_views, n_u, n_v = 9, 41, 77
+    gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+    views = gen(76, n_views, shape, n_u, n_v)
+    G = gjp.Geometry(shape, views, n_u, n_v, beam=beam, weight=weight, clip_cylinder=clip)
+    og = _oracle_geom(oracle_mod, G)
+    vol = workloads.rasterize(workloads.random_ellipsoids(77, shape), shape)
+    note(f"naive forward {beam} {weight} clip={clip}")
+    tv = _to_dev(vol, dev)
+    y = gjp.forward_naive(tv, G).cpu().numpy()
+    assert rel_l2(y, oracle_mod.forward(og, vol)) <= TOL32
+    y_tuned = gjp.forward(tv, G).cpu().numpy()
+    assert rel_l2(y, y_tuned) <= 1e-6
+    note(f"naive vs tuned: {int(np.sum(y != y_tuned))} of {y.size} values differ in rounding")
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_naive_forward_16bit(gjp, oracle_mod, dtype):
+    import torch
+    dev = cuda()
+    cfg = workloads.config("c1")
+    vol = workloads.rasterize(cfg.phantom_ellipsoids(), cfg.shape)
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float16
+    v16 = _to_dev(vol, dev).to(tdt)
+    G = gjp.Geometry.from_config(cfg)
+    note(f"naive forward c1 {dtype}")
+    y = gjp.forward_naive(v16, G).cpu().numpy()
+    og = oracle_mod.geometry_for(cfg)
+    assert rel_l2(y, oracle_mod.forward(og, v16.float().cpu().numpy())) <= TOL32
+    assert rel_l2(y, oracle_mod.forward(og, vol)) <= TOL16

@@ -65,3 +65,20 @@ def test_profile_summary(tmp_path):
     data = json.loads(out_js.read_text())
     assert data["source_sha256"] == profiling.source_hash()
     assert data["kernels"]["forward_f32"]["fetch_bytes_per_launch"] == 1000.0 * 1024 * 2.0
+
+
+def test_profile_kernel_names():
+    from paper_1609_00958_amd import profiling
+    want = {
+        "void gjp::fwd_kernel<float, 0, false>(gjp::FwdArgs)": "forward_f32",
+        "void gjp::fwd_kernel<gjp::bf16_t, 0, false>(gjp::FwdArgs)": "forward_bf16",
+        "void gjp::batched_fwd_kernel<float, 0, false>(gjp::BatchInst const*)": "batched",
+        "void gjp::naive_fwd_kernel<float, 0>(gjp::GridGeom, double const*)": "forward_naive_f32",
+        "void gjp::naive_fwd_kernel<gjp::f16_t, 1>(gjp::GridGeom)": "forward_naive_f16",
+        "void gjp::batched_pad_kernel(gjp::BatchInst const*)": "batched_pad",
+        "void gjp::pad_kernel<unsigned int>(unsigned int const*)": "pad",
+        "void gjp::adj_gather_sep_kernel<0>(gjp::GridGeom)": "adjoint_gather",
+        "elementwise_kernel<...>": None,
+    }
+    for name, short in want.items():
+        assert profiling.short_name(name) == short, name
