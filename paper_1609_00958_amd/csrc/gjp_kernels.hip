@@ -114,12 +114,25 @@ __device__ __forceinline__ void ptr_pair(const T* p, float& x0, float& x1) {
   widen2(*reinterpret_cast<const u1a4*>(p), p, x0, x1);
 }
 
+// -0.0f in a scalar register, opaque to the compiler: w * v is issued as the
+// fused w * v + (-0), which gives the identical result for every w and v, and
+// for 16-bit storage takes the half-precision value directly (mixed-precision
+// FMA) instead of a separate conversion.
+__device__ __forceinline__ float opaque_neg_zero() {
+  float z;
+  asm("s_mov_b32 %0, 0x80000000" : "=s"(z));
+  return z;
+}
+
 // acc += wfa (wfb v(a, z) + wcb v(a, z+1)) + wca (wfb v(a+1, z) + wcb v(a+1, z+1)),
 // as two fused steps in this order (Eq. 13 with the weights of Eqs. 10-12).
 __device__ __forceinline__ float accumulate4(float acc, float wfa, float wca, float wfb,
                                              float wcb, const Quad& q) {
-  acc = __builtin_fmaf(wfa, __builtin_fmaf(wfb, q.a0z0, wcb * q.a0z1), acc);
-  acc = __builtin_fmaf(wca, __builtin_fmaf(wfb, q.a1z0, wcb * q.a1z1), acc);
+  const float nz = opaque_neg_zero();
+  const float r0 = __builtin_fmaf(wfb, q.a0z0, __builtin_fmaf(wcb, q.a0z1, nz));
+  const float r1 = __builtin_fmaf(wfb, q.a1z0, __builtin_fmaf(wcb, q.a1z1, nz));
+  acc = __builtin_fmaf(wfa, r0, acc);
+  acc = __builtin_fmaf(wca, r1, acc);
   return acc;
 }
 
@@ -256,26 +269,46 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// One plane of the row-uniform loop. q = {row byte offset, wfa, wca, plane
-// index as a float} of the plane (wave-uniform); CHECK zeroes the axis-2 weights of lanes whose sample
-// range excludes the plane (the load stays in bounds: the row is inside the
-// copy and the axis-2 coordinate is clamped). A zeroed plane adds +-0, so the
-// lane's sum is unchanged.
-template <typename T, int WF, bool CHECK>
-__device__ __forceinline__ void ru_plane(__amdgpu_buffer_rsrc_t rs, const float4 q, int i,
-                                         const RaySetup& R, float hib, float& acc) {
+// NP consecutive planes i .. i + NP - 1 of the row-uniform loop, slots[k] =
+// {row byte offset, wfa, wca, plane index as a float} of plane i + k
+// (wave-uniform). All NP wide loads are issued before the first is consumed,
+// so each lane keeps NP loads in flight. CHECK zeroes the row weights of
+// lanes whose sample range excludes a plane (the load stays in bounds: the row
+// is inside the copy and the axis-2 coordinate is clamped); a zeroed plane
+// adds +-0, so the lane's sum is unchanged.
+template <typename T, int WF, bool CHECK, int NP>
+__device__ __forceinline__ void ru_planes(__amdgpu_buffer_rsrc_t rs, const float4* slots, int i,
+                                          const RaySetup& R, float hib, float& acc) {
   constexpr uint32_t pe = 2 * sizeof(T);
-  int ib;
-  float wfb, wcb;
-  sample_axis<WF>(q.w, R.gb, R.cb, hib, ib, wfb, wcb);
-  if (CHECK) {
-    const bool in = i >= R.i0 && i < R.i1;
-    wfb = in ? wfb : 0.0f;
-    wcb = in ? wcb : 0.0f;
+  float4 q[NP];
+  Quad u[NP];
+  float wfb[NP], wcb[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) q[k] = slots[k];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    int ib;
+    sample_axis<WF>(q[k].w, R.gb, R.cb, hib, ib, wfb[k], wcb[k]);
+    const uint32_t vo = (uint32_t)(ib + 1) * pe + __float_as_uint(q[k].x);
+    u[k] = buf_quad(rs, vo, 0, (const T*)nullptr);
   }
-  const uint32_t vo = (uint32_t)(ib + 1) * pe + __float_as_uint(q.x);
-  acc = accumulate4(acc, q.y, q.z, wfb, wcb, buf_quad(rs, vo, 0, (const T*)nullptr));
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    float wfa = q[k].y, wca = q[k].z;
+    if (CHECK) {
+      const bool in = i + k >= R.i0 && i + k < R.i1;
+      wfa = in ? wfa : 0.0f;
+      wca = in ? wca : 0.0f;
+    }
+    acc = accumulate4(acc, wfa, wca, wfb[k], wcb[k], u[k]);
+  }
 }
+
+// Planes per group of the row-uniform loop.
+#ifndef GJP_RU_GROUP
+#define GJP_RU_GROUP 4
+#endif
+constexpr int kRuGroup = GJP_RU_GROUP;
 
 // Sampling loop for a wavefront whose rays all share the driving axis m (0 or
 // 1) and the in-plane coefficients (ca, ga): the row coordinate, its weights
@@ -323,23 +356,15 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
     const int j0 = min(max(mid_lo - base, 0), cnt);
     const int j1 = min(max(mid_hi - base, j0), cnt);
     int j = 0;
-    for (; j < j0; ++j) ru_plane<T, WF, true>(rs, slots[j], base + j, R, hib, acc);
-    // two planes per iteration: both wide loads are issued first
-    for (; j + 1 < j1; j += 2) {
-      const float4 q0 = slots[j], q1 = slots[j + 1];
-      int ib0, ib1;
-      float wfb0, wcb0, wfb1, wcb1;
-      sample_axis<WF>(q0.w, R.gb, R.cb, hib, ib0, wfb0, wcb0);
-      sample_axis<WF>(q1.w, R.gb, R.cb, hib, ib1, wfb1, wcb1);
-      const uint32_t vo0 = (uint32_t)(ib0 + 1) * pe + __float_as_uint(q0.x);
-      const uint32_t vo1 = (uint32_t)(ib1 + 1) * pe + __float_as_uint(q1.x);
-      const Quad u0 = buf_quad(rs, vo0, 0, (const T*)nullptr);
-      const Quad u1 = buf_quad(rs, vo1, 0, (const T*)nullptr);
-      acc = accumulate4(acc, q0.y, q0.z, wfb0, wcb0, u0);
-      acc = accumulate4(acc, q1.y, q1.z, wfb1, wcb1, u1);
-    }
-    for (; j < j1; ++j) ru_plane<T, WF, false>(rs, slots[j], base + j, R, hib, acc);
-    for (; j < cnt; ++j) ru_plane<T, WF, true>(rs, slots[j], base + j, R, hib, acc);
+    for (; j + kRuGroup <= j0; j += kRuGroup)
+      ru_planes<T, WF, true, kRuGroup>(rs, slots + j, base + j, R, hib, acc);
+    for (; j < j0; ++j) ru_planes<T, WF, true, 1>(rs, slots + j, base + j, R, hib, acc);
+    for (; j + kRuGroup <= j1; j += kRuGroup)
+      ru_planes<T, WF, false, kRuGroup>(rs, slots + j, base + j, R, hib, acc);
+    for (; j < j1; ++j) ru_planes<T, WF, false, 1>(rs, slots + j, base + j, R, hib, acc);
+    for (; j + kRuGroup <= cnt; j += kRuGroup)
+      ru_planes<T, WF, true, kRuGroup>(rs, slots + j, base + j, R, hib, acc);
+    for (; j < cnt; ++j) ru_planes<T, WF, true, 1>(rs, slots + j, base + j, R, hib, acc);
     // every lane has read the slots before the next block rewrites them
     __builtin_amdgcn_wave_barrier();
   }

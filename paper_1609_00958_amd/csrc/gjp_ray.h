@@ -240,13 +240,13 @@ __device__ __forceinline__ void sample_axis(float fi, float g, float c, float hi
   p = __builtin_amdgcn_fmed3f(p, -1.0f, hi);
   const float f = __builtin_floorf(p);
   const float d = p - f;
+  i_fl = (int)f;
   w_fl = weight_fn<WF>(d);
   // complementary weight (Eq. 12); for the linear weight 1 - (1 - d) is d
   if constexpr (WF == W_LINEAR)
     w_cl = d;
   else
     w_cl = 1.0f - w_fl;
-  i_fl = (int)f;
 }
 
 }  // namespace gjp
