@@ -158,9 +158,11 @@ gjp_status gjp_views_parallel(int32_t n_views, double pitch_u, double pitch_v, i
    the ray-sample count of the throughput metric. Errors: GJP_EINVAL. */
 gjp_status gjp_count_samples(const gjp_geometry *g, uint64_t *out);
 
-/* Select the ray-tile shape of gjp_forward_project for this geometry and
-   dtype by timing each candidate on `stream` with the caller's buffers
-   (d_sino is overwritten). The choice is kept in a process-wide cache keyed
+/* Select the launch configuration of gjp_forward_project for this geometry
+   and dtype (ray-tile shape, views interleaved per tile, planes whose loads a
+   lane issues together) by timing candidates on `stream` with the caller's
+   buffers (d_sino is overwritten); every configuration gives bitwise
+   identical sinograms. The choice is kept in a process-wide cache keyed
    by the geometry's shape signature and dtype and used by later forward and
    batched calls. *tile_v_out receives the chosen number of detector pixels
    along v per wavefront row (64, 32 or 16). Synchronises `stream`.
@@ -168,11 +170,15 @@ gjp_status gjp_count_samples(const gjp_geometry *g, uint64_t *out);
 gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
                                 float *d_sino, void *stream, int32_t *tile_v_out);
 
-/* Fix the ray-tile shape that forward and batched calls use for geometries
-   of this shape signature and dtype, as gjp_autotune_forward would (tile_v =
-   detector pixels along v per wavefront row: 64, 32 or 16). Every tile shape
-   gives bitwise identical sinograms. Host-only. Errors: GJP_EINVAL. */
-gjp_status gjp_set_forward_tile(const gjp_geometry *g, int32_t vol_dtype, int32_t tile_v);
+/* Fix the launch configuration that forward calls (and, for the tile shape
+   and view group, batched calls) use for geometries of this shape signature
+   and dtype, as gjp_autotune_forward would: tile_v = detector pixels along v
+   per wavefront row (64, 32 or 16); view_group = consecutive views that take
+   their turn on each ray tile together (1 to 64); load_group = planes whose
+   volume loads a lane issues together (2 or 4). Every configuration gives
+   bitwise identical sinograms. Host-only. Errors: GJP_EINVAL. */
+gjp_status gjp_set_forward_tile(const gjp_geometry *g, int32_t vol_dtype, int32_t tile_v,
+                                int32_t view_group, int32_t load_group);
 
 /* SART (the reconstruction of Sec. IV-B, after Andersen and Kak): the two
    elementwise steps of one subset update

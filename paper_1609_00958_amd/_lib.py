@@ -77,7 +77,7 @@ def lib():
     L.gjp_views_parallel.argtypes = [i32, f64, f64, i32, i32, f64p]
     L.gjp_count_samples.argtypes = [vp, ctypes.POINTER(u64)]
     L.gjp_autotune_forward.argtypes = [vp, vp, i32, vp, vp, ctypes.POINTER(i32)]
-    L.gjp_set_forward_tile.argtypes = [vp, i32, i32]
+    L.gjp_set_forward_tile.argtypes = [vp, i32, i32, i32, i32]
     L.gjp_timing_enable.argtypes = [i32]
     L.gjp_timing_reset.argtypes = []
     L.gjp_timing_read.argtypes = [ctypes.c_char_p, f64p, ctypes.POINTER(i64)]

@@ -555,6 +555,7 @@ void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* pad
   a.tile_v_log2 = tile.tile_v_log2;
   a.remap = tile.remap;
   a.view_group = tile.view_group < 1 ? 1 : tile.view_group;
+  a.ru_group = tile.ru_group == 2 ? 2 : 4;
   a.n_views = g->n_views;
   const int tile_v = 1 << tile.tile_v_log2;
   const int tile_u = 256 >> tile.tile_v_log2;
@@ -662,28 +663,44 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
   GJP_HIP(hipEventCreate(&e1), "autotune event");
   FwdTile best;
   float best_ms = 3.0e38f;
+  // time one candidate: a warm-up call, then three timed calls
+  auto trial = [&](const FwdTile& t) -> gjp_status {
+    gjp_status r = forward_with_tile(g, d_vol, vol_dtype, d_sino, s, t);  // warm-up
+    if (r != GJP_OK) return r;
+    hipError_t he = hipEventRecord(e0, s);
+    const int reps = 3;
+    for (int i = 0; i < reps && r == GJP_OK && he == hipSuccess; ++i)
+      r = forward_with_tile(g, d_vol, vol_dtype, d_sino, s, t);
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (r != GJP_OK) return r;
+    if (he != hipSuccess) return hip_fail(he, "autotune timing");
+    float ms = 0.0f;
+    he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) return hip_fail(he, "autotune elapsed");
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+    return GJP_OK;
+  };
+  // tile shape and view group with four-plane load groups, then two-plane
+  // groups for the best of them
   for (int k : {6, 5, 4}) {
     for (int vg : {8, 16, 1}) {
       FwdTile t;
       t.tile_v_log2 = k;
       t.view_group = vg;
-      st = forward_with_tile(g, d_vol, vol_dtype, d_sino, s, t);  // warm-up
+      t.ru_group = 4;
+      st = trial(t);
       if (st != GJP_OK) break;
-      GJP_HIP(hipEventRecord(e0, s), "autotune record");
-      const int reps = 3;
-      for (int r = 0; r < reps && st == GJP_OK; ++r)
-        st = forward_with_tile(g, d_vol, vol_dtype, d_sino, s, t);
-      GJP_HIP(hipEventRecord(e1, s), "autotune record");
-      GJP_HIP(hipEventSynchronize(e1), "autotune sync");
-      if (st != GJP_OK) break;
-      float ms = 0.0f;
-      GJP_HIP(hipEventElapsedTime(&ms, e0, e1), "autotune elapsed");
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = t;
-      }
     }
     if (st != GJP_OK) break;
+  }
+  if (st == GJP_OK) {
+    FwdTile t = best;
+    t.ru_group = 2;
+    st = trial(t);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -697,7 +714,8 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
 }
 
 extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dtype,
-                                           int32_t tile_v) {
+                                           int32_t tile_v, int32_t view_group,
+                                           int32_t load_group) {
   if (!g) return fail(GJP_EINVAL, "gjp_set_forward_tile: geometry is null");
   if (vol_dtype != GJP_F32 && vol_dtype != GJP_BF16 && vol_dtype != GJP_F16)
     return fail(GJP_EINVAL, "gjp_set_forward_tile: unknown dtype");
@@ -706,6 +724,12 @@ extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dt
   else if (tile_v == 32) t.tile_v_log2 = 5;
   else if (tile_v == 16) t.tile_v_log2 = 4;
   else return fail(GJP_EINVAL, "gjp_set_forward_tile: tile_v must be 64, 32 or 16");
+  if (view_group < 1 || view_group > 64)
+    return fail(GJP_EINVAL, "gjp_set_forward_tile: view_group must be in [1, 64]");
+  if (load_group != 2 && load_group != 4)
+    return fail(GJP_EINVAL, "gjp_set_forward_tile: load_group must be 2 or 4");
+  t.view_group = view_group;
+  t.ru_group = load_group;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[tune_key(g, vol_dtype)] = t;
   return GJP_OK;

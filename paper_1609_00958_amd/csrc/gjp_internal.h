@@ -60,6 +60,7 @@ struct FwdTile {
   int tile_v_log2 = 6;  // detector pixels along v per wavefront row (64, 32, 16)
   int remap = 1;        // 1: contiguous tile ranges per XCD
   int view_group = 8;   // consecutive views that share each tile's turn
+  int ru_group = 4;     // planes whose wide loads a lane issues together (2 or 4)
 };
 
 // Arguments of one forward launch (one volume, a range of views).
@@ -77,6 +78,7 @@ struct FwdArgs {
   int n_views;          // views of this launch
   int tiles_v, tiles_u, tiles_per_view;
   int remap;
+  int ru_group;         // planes per load group of the row-uniform loop (2 or 4)
 };
 
 // Device views of a geometry on the current device (uploads on first use).

@@ -304,11 +304,9 @@ __device__ __forceinline__ void ru_planes(__amdgpu_buffer_rsrc_t rs, const float
   }
 }
 
-// Planes per group of the row-uniform loop.
-#ifndef GJP_RU_GROUP
-#define GJP_RU_GROUP 4
-#endif
-constexpr int kRuGroup = GJP_RU_GROUP;
+// Planes per load group of the row-uniform loop in the batched launch (the
+// single launch takes it from its arguments; the sums do not depend on it).
+constexpr int kBatchRuGroup = 4;
 
 // Sampling loop for a wavefront whose rays all share the driving axis m (0 or
 // 1) and the in-plane coefficients (ca, ga): the row coordinate, its weights
@@ -323,7 +321,7 @@ constexpr int kRuGroup = GJP_RU_GROUP;
 // arithmetic, as fwd_loop_buf, so the sums are identical (up to the sign of a
 // zero). Every one of the 64 lanes must take part; the sums of lanes without
 // samples are meaningless and must be discarded by the caller.
-template <typename T, int WF>
+template <typename T, int WF, int GRP>
 __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const RaySetup& R, int m,
                                                      float ca, float ga, int lo, int hi,
                                                      int mid_lo, int mid_hi) {
@@ -356,14 +354,14 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
     const int j0 = min(max(mid_lo - base, 0), cnt);
     const int j1 = min(max(mid_hi - base, j0), cnt);
     int j = 0;
-    for (; j + kRuGroup <= j0; j += kRuGroup)
-      ru_planes<T, WF, true, kRuGroup>(rs, slots + j, base + j, R, hib, acc);
+    for (; j + GRP <= j0; j += GRP)
+      ru_planes<T, WF, true, GRP>(rs, slots + j, base + j, R, hib, acc);
     for (; j < j0; ++j) ru_planes<T, WF, true, 1>(rs, slots + j, base + j, R, hib, acc);
-    for (; j + kRuGroup <= j1; j += kRuGroup)
-      ru_planes<T, WF, false, kRuGroup>(rs, slots + j, base + j, R, hib, acc);
+    for (; j + GRP <= j1; j += GRP)
+      ru_planes<T, WF, false, GRP>(rs, slots + j, base + j, R, hib, acc);
     for (; j < j1; ++j) ru_planes<T, WF, false, 1>(rs, slots + j, base + j, R, hib, acc);
-    for (; j + kRuGroup <= cnt; j += kRuGroup)
-      ru_planes<T, WF, true, kRuGroup>(rs, slots + j, base + j, R, hib, acc);
+    for (; j + GRP <= cnt; j += GRP)
+      ru_planes<T, WF, true, GRP>(rs, slots + j, base + j, R, hib, acc);
     for (; j < cnt; ++j) ru_planes<T, WF, true, 1>(rs, slots + j, base + j, R, hib, acc);
     // every lane has read the slots before the next block rewrites them
     __builtin_amdgcn_wave_barrier();
@@ -374,7 +372,7 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
 // One ray per lane. All 64 lanes of the wavefront call this together; a lane
 // whose pixel lies outside the detector (valid == false) takes part in the
 // wavefront-wide steps with an empty sample range and stores nothing.
-template <typename T, int WF, bool IDX64>
+template <typename T, int WF, bool IDX64, int GRP>
 __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv, bool valid) {
   RaySetup R;
   ray_setup(a.views + 12 * (size_t)view, a.G, iu, iv, R);
@@ -399,7 +397,7 @@ __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int 
     const int hi = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i1 : -1));
     const int mid_lo = __builtin_amdgcn_readfirstlane(wave_max(has ? R.i0 : -1));
     const int mid_hi = __builtin_amdgcn_readfirstlane(wave_min(has ? R.i1 : 0x7fffffff));
-    acc = fwd_loop_rowuniform<T, WF>(a, R, lm, lca, lga, lo, hi, mid_lo, mid_hi);
+    acc = fwd_loop_rowuniform<T, WF, GRP>(a, R, lm, lca, lga, lo, hi, mid_lo, mid_hi);
     if (!has) acc = 0.0f;
   } else if (R.m != 2) {
     if constexpr (!IDX64)
@@ -429,7 +427,7 @@ __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int 
   if (valid) a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
 }
 
-template <typename T, int WF, bool IDX64>
+template <typename T, int WF, bool IDX64, int GRP>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
   const int tu = t / a.tiles_v;
   const int tv = t - tu * a.tiles_v;
@@ -440,14 +438,14 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
   const int iv = (tv << k) + (lane & ((1 << k) - 1));
   const int iu = tu * (4 * rows) + wave * rows + (lane >> k);
   const bool valid = iu < a.n_u && iv < a.n_v;
-  fwd_ray<T, WF, IDX64>(a, view, valid ? iu : 0, valid ? iv : 0, valid);
+  fwd_ray<T, WF, IDX64, GRP>(a, view, valid ? iu : 0, valid ? iv : 0, valid);
 }
 
 // Launch order: groups of view_group consecutive views; within a group each
 // tile comes up for all the group's views in turn. Rays of nearby views cross
 // nearly the same voxels, so the workgroups resident on an XCD share their
 // volume reads in L2 instead of each view streaming the volume again.
-template <typename T, int WF, bool IDX64>
+template <typename T, int WF, bool IDX64, int GRP>
 __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
   uint32_t b = blockIdx.x;
   if (a.remap) b = xcd_remap(b, gridDim.x);
@@ -457,7 +455,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
   const uint32_t v0 = grp * K;
   const uint32_t kg = min(K, (uint32_t)a.n_views - v0);  // views in this group
   const uint32_t t = r / kg;
-  fwd_tile<T, WF, IDX64>(a, (int)(v0 + (r - t * kg)), (int)t);
+  fwd_tile<T, WF, IDX64, GRP>(a, (int)(v0 + (r - t * kg)), (int)t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1089,7 +1087,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void b
     const uint2 it = items[item];
     const int inst = (int)(it.x & 0xfffu);
     const int view = (int)(it.x >> 12);
-    fwd_tile<T, WF, IDX64>(insts[inst].a, view, (int)it.y);
+    fwd_tile<T, WF, IDX64, kBatchRuGroup>(insts[inst].a, view, (int)it.y);
   }
 }
 
@@ -1177,10 +1175,17 @@ int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int
 
 template <typename T, int WF>
 static void launch_fwd_t(const FwdArgs& a, bool idx64, unsigned grid, hipStream_t s) {
-  if (idx64)
-    fwd_kernel<T, WF, true><<<grid, 256, 0, s>>>(a);
-  else
-    fwd_kernel<T, WF, false><<<grid, 256, 0, s>>>(a);
+  if (a.ru_group == 2) {
+    if (idx64)
+      fwd_kernel<T, WF, true, 2><<<grid, 256, 0, s>>>(a);
+    else
+      fwd_kernel<T, WF, false, 2><<<grid, 256, 0, s>>>(a);
+  } else {
+    if (idx64)
+      fwd_kernel<T, WF, true, 4><<<grid, 256, 0, s>>>(a);
+    else
+      fwd_kernel<T, WF, false, 4><<<grid, 256, 0, s>>>(a);
+  }
 }
 
 int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,

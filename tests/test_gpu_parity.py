@@ -264,12 +264,15 @@ def test_circular_tiles_bitwise_and_adjoint(gjp, oracle_mod, beam):
     vol = workloads.rasterize(workloads.random_ellipsoids(111, shape), shape)
     x = _to_dev(vol, dev)
     outs = []
+    configs = [(64, 8, 4), (64, 8, 2), (64, 1, 4), (64, 16, 2), (32, 8, 4), (16, 3, 2)]
     for dt in (torch.float32, torch.bfloat16):
-        for tv in (64, 32, 16):
-            gjp.set_forward_tile(G, dt, tv)
-            note(f"circular {beam} tile {tv} {dt}")
-            outs.append(gjp.forward(x.to(dt), G))
-        assert torch.equal(outs[-3], outs[-2]) and torch.equal(outs[-3], outs[-1])
+        got = []
+        for tv, vg, lg in configs:
+            gjp.set_forward_tile(G, dt, tv, vg, lg)
+            note(f"circular {beam} tile {tv} views {vg} loads {lg} {dt}")
+            got.append(gjp.forward(x.to(dt), G))
+        assert all(torch.equal(got[0], o) for o in got[1:])
+        outs.append(got[0])
     assert rel_l2(outs[0].cpu().numpy(), oracle_mod.forward(og, vol)) <= TOL32
     y = np.random.default_rng(112).uniform(0, 1, size=G.sino_shape).astype(np.float32)
     note(f"circular {beam} adjoint")
