@@ -557,8 +557,9 @@ void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* pad
   a.view_group = tile.view_group < 1 ? 1 : tile.view_group;
   a.ru_group = tile.ru_group == 2 ? 2 : 4;
   a.n_views = g->n_views;
+  // k = 7: 128 pixels along v per wavefront row (two per lane), four rows
   const int tile_v = 1 << tile.tile_v_log2;
-  const int tile_u = 256 >> tile.tile_v_log2;
+  const int tile_u = tile.tile_v_log2 == 7 ? 4 : 256 >> tile.tile_v_log2;
   a.tiles_v = (g->n_v + tile_v - 1) / tile_v;
   a.tiles_u = (g->n_u + tile_u - 1) / tile_u;
   a.tiles_per_view = a.tiles_v * a.tiles_u;
@@ -686,7 +687,10 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
   };
   // tile shape and view group with four-plane load groups, then two-plane
   // groups for the best of them
-  for (int k : {6, 5, 4}) {
+  // two rays per lane (k = 7) only for 16-bit storage
+  const bool pairs = vol_dtype != GJP_F32;
+  for (int k : {7, 6, 5, 4}) {
+    if (k == 7 && !pairs) continue;
     for (int vg : {8, 16, 1}) {
       FwdTile t;
       t.tile_v_log2 = k;
@@ -720,10 +724,13 @@ extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dt
   if (vol_dtype != GJP_F32 && vol_dtype != GJP_BF16 && vol_dtype != GJP_F16)
     return fail(GJP_EINVAL, "gjp_set_forward_tile: unknown dtype");
   FwdTile t;
-  if (tile_v == 64) t.tile_v_log2 = 6;
+  if (tile_v == 128 && vol_dtype != GJP_F32) t.tile_v_log2 = 7;
+  else if (tile_v == 64) t.tile_v_log2 = 6;
   else if (tile_v == 32) t.tile_v_log2 = 5;
   else if (tile_v == 16) t.tile_v_log2 = 4;
-  else return fail(GJP_EINVAL, "gjp_set_forward_tile: tile_v must be 64, 32 or 16");
+  else
+    return fail(GJP_EINVAL,
+                "gjp_set_forward_tile: tile_v must be 64, 32 or 16 (or 128 for 16-bit storage)");
   if (view_group < 1 || view_group > 64)
     return fail(GJP_EINVAL, "gjp_set_forward_tile: view_group must be in [1, 64]");
   if (load_group != 2 && load_group != 4)
@@ -888,6 +895,8 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
     const FwdTile tile = tile_for(g[i], dtypes[i]);
     FwdTile t2 = tile;
     t2.remap = 0;
+    // the batched launch runs one ray per lane (same sums as two per lane)
+    if (t2.tile_v_log2 > 6) t2.tile_v_log2 = 6;
     fill_fwd_args(g[i], d_views, nullptr, nullptr, t2, I.a);
     I.padded = static_cast<char*>(P->padded_all) + pad_off[i];
     set_padded(I.a, I.padded, dtypes[i], g[i]->n);

@@ -369,14 +369,12 @@ __device__ __forceinline__ float fwd_loop_rowuniform(const FwdArgs& a, const Ray
   return acc;
 }
 
-// One ray per lane. All 64 lanes of the wavefront call this together; a lane
-// whose pixel lies outside the detector (valid == false) takes part in the
-// wavefront-wide steps with an empty sample range and stores nothing.
+// Sum of one ray per lane (before the step length). All 64 lanes of the
+// wavefront call this together; a lane without samples (R.i0 == R.i1, e.g. a
+// pixel outside the detector) takes part in the wavefront-wide steps and its
+// sum is meaningless.
 template <typename T, int WF, bool IDX64, int GRP>
-__device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv, bool valid) {
-  RaySetup R;
-  ray_setup(a.views + 12 * (size_t)view, a.G, iu, iv, R);
-  if (!valid) R.i1 = R.i0;
+__device__ __forceinline__ float fwd_sum(const FwdArgs& a, const RaySetup& R) {
   float acc = 0.0f;
   // row-uniform wavefront: every lane with samples shares m (0 or 1), ca and
   // ga; the shared values are the first such lane's
@@ -424,16 +422,266 @@ __device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int 
       fi += 1.0f;
     }
   }
-  if (valid) a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
+  return acc;
 }
 
 template <typename T, int WF, bool IDX64, int GRP>
+__device__ __forceinline__ void fwd_ray(const FwdArgs& a, int view, int iu, int iv, bool valid) {
+  RaySetup R;
+  ray_setup(a.views + 12 * (size_t)view, a.G, iu, iv, R);
+  if (!valid) R.i1 = R.i0;
+  const float acc = fwd_sum<T, WF, IDX64, GRP>(a, R);
+  if (valid) a.sino[((size_t)view * a.n_u + iu) * a.n_v + iv] = acc * R.scale;
+}
+
+// Three consecutive pair elements at byte offset voff of a 16-bit copy: the
+// samples at axis-2 floors z (elements 0, 1) and z + 1 (elements 1, 2).
+struct Triple {
+  uint32_t e0, e1, e2;
+};
+__device__ __forceinline__ Triple buf_triple(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  typedef uint32_t u3v __attribute__((ext_vector_type(3)));
+  const u3v v = __builtin_bit_cast(u3v, __builtin_amdgcn_raw_buffer_load_b96(r, voff, 0, 0));
+  return {v.x, v.y, v.z};
+}
+
+// Row-uniform loop over two rays per lane for 16-bit storage. The two rays of
+// a lane share the driving axis and the in-plane coefficients with every
+// other ray of the wavefront (one detector column), so on each plane they
+// share the row, its weights and its offset, and the caller has checked that
+// on every plane of [lo, hi) the second ray's axis-2 coordinate exceeds the
+// first's by less than one voxel (so its floor is the first's or one more).
+// One 12-byte load of the pair elements at floors z, z + 1, z + 2 of the first
+// ray then serves both. Each ray accumulates exactly the terms, in the same
+// order and with the same arithmetic, as the one-ray loop.
+#ifndef GJP_PAIR_GROUP
+#define GJP_PAIR_GROUP 2
+#endif
+constexpr int kPairGroup = GJP_PAIR_GROUP;  // planes per load group (two samples each)
+
+template <typename T, int WF, int GRP>
+__device__ __forceinline__ void fwd_loop_rowuniform_pair(const FwdArgs& a, const RaySetup& R1,
+                                                         const RaySetup& R2, int m, float ca,
+                                                         float ga, int lo, int hi, int mid_lo,
+                                                         int mid_hi, float& acc1, float& acc2) {
+  constexpr uint32_t pe = 2 * sizeof(T);
+  __shared__ float4 s_planes[4][64];
+  float4* slots = s_planes[threadIdx.x >> 6];
+  const char* copy = static_cast<const char*>(m == 0 ? a.vol_a : a.vol_b);
+  const unsigned long long Sm = (unsigned long long)(m == 0 ? a.S0 : a.S1) * pe;
+  const unsigned long long Sa = (unsigned long long)(m == 0 ? a.S1 : a.S0) * pe;
+  const float hia = (m == 0) ? a.G.hi[1] : a.G.hi[0];
+  const float hib = a.G.hi[2];
+  const int lane = (int)(threadIdx.x & 63);
+  acc1 = 0.0f;
+  acc2 = 0.0f;
+  for (int base = lo; base < hi; base += 64) {
+    int ia_l;
+    float wfa_l, wca_l;
+    sample_axis<WF>((float)(base + lane), ga, ca, hia, ia_l, wfa_l, wca_l);
+    const int ia_min = __builtin_amdgcn_readfirstlane(wave_min(ia_l));
+    const unsigned long long org = (unsigned long long)(base + 1) * Sm +
+                                   (unsigned long long)(ia_min + 1) * Sa;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(copy + org), (short)0,
+        (int)(uint32_t)min(a.copy_bytes - org, 0xffffffffull), 0x00020000);
+    const uint32_t row_l = (uint32_t)((unsigned long long)lane * Sm +
+                                      (unsigned long long)(ia_l - ia_min) * Sa);
+    slots[lane] = make_float4(__uint_as_float(row_l), wfa_l, wca_l, (float)(base + lane));
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = min(64, hi - base);
+    const int j0 = min(max(mid_lo - base, 0), cnt);
+    const int j1 = min(max(mid_hi - base, j0), cnt);
+    // planes [j0, j1) lie inside both rays' ranges on every lane
+    auto group = [&](int j, auto check_tag, auto np_tag) {
+      constexpr bool CHECK = decltype(check_tag)::value;
+      constexpr int NP = decltype(np_tag)::value;
+      float4 q[NP];
+      Triple u[NP];
+      float wfb1[NP], wcb1[NP], wfb2[NP], wcb2[NP];
+      bool up[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) q[k] = slots[j + k];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        int ib1, ib2;
+        sample_axis<WF>(q[k].w, R1.gb, R1.cb, hib, ib1, wfb1[k], wcb1[k]);
+        sample_axis<WF>(q[k].w, R2.gb, R2.cb, hib, ib2, wfb2[k], wcb2[k]);
+        up[k] = ib2 != ib1;
+        const uint32_t vo = (uint32_t)(ib1 + 1) * pe + __float_as_uint(q[k].x);
+        u[k] = buf_triple(rs, vo);
+      }
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        float wfa1 = q[k].y, wca1 = q[k].z, wfa2 = q[k].y, wca2 = q[k].z;
+        if (CHECK) {
+          const int i = base + j + k;
+          const bool in1 = i >= R1.i0 && i < R1.i1, in2 = i >= R2.i0 && i < R2.i1;
+          wfa1 = in1 ? wfa1 : 0.0f;
+          wca1 = in1 ? wca1 : 0.0f;
+          wfa2 = in2 ? wfa2 : 0.0f;
+          wca2 = in2 ? wca2 : 0.0f;
+        }
+        const u2v d1 = {u[k].e0, u[k].e1};
+        const u2v d2 = {up[k] ? u[k].e1 : u[k].e0, up[k] ? u[k].e2 : u[k].e1};
+        acc1 = accumulate4(acc1, wfa1, wca1, wfb1[k], wcb1[k], widen4(d1, (const T*)nullptr));
+        acc2 = accumulate4(acc2, wfa2, wca2, wfb2[k], wcb2[k], widen4(d2, (const T*)nullptr));
+      }
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    using two = std::integral_constant<int, kPairGroup>;
+    using one = std::integral_constant<int, 1>;
+    int j = 0;
+    for (; j + kPairGroup <= j0; j += kPairGroup) group(j, yes(), two());
+    for (; j < j0; ++j) group(j, yes(), one());
+    for (; j + kPairGroup <= j1; j += kPairGroup) group(j, no(), two());
+    for (; j < j1; ++j) group(j, no(), one());
+    for (; j + kPairGroup <= cnt; j += kPairGroup) group(j, yes(), two());
+    for (; j < cnt; ++j) group(j, yes(), one());
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Two rays per lane, pixels (iu, iv) and (iu, iv + 1) of one detector column
+// (16-bit storage). When the wavefront is row-uniform and the two rays' axis-2
+// coordinates stay less than a voxel apart on every plane (checked here, with
+// a margin for single-precision rounding), one load serves both rays' samples;
+// otherwise each ray set runs the one-ray path. The sums are the one-ray
+// path's in every case.
+template <typename T, int WF, bool IDX64, int GRP>
+__device__ __forceinline__ void fwd_ray_pair(const FwdArgs& a, int view, int iu, int iv,
+                                             bool valid1, bool valid2) {
+  RaySetup R1, R2;
+  const double* vv = a.views + 12 * (size_t)view;
+  {
+    // the first ray's setup waits in LDS while the second one's double
+    // precision setup runs, so that the two are never live in registers
+    // together (the register peak of this kernel)
+    __shared__ float4 s_stash[2][256];
+    RaySetup T1;
+    ray_setup(vv, a.G, iu, iv, T1);
+    s_stash[0][threadIdx.x] = make_float4(T1.ca, T1.ga, T1.cb, T1.gb);
+    s_stash[1][threadIdx.x] = make_float4(__int_as_float(T1.m), __int_as_float(T1.i0),
+                                          __int_as_float(T1.i1), T1.scale);
+    // compiler barriers: the second setup starts after the stash is written
+    // (its pixel index passes through the barrier) and the stash is read
+    // back after the second setup has finished
+    int iv2 = iv + 1;
+    asm volatile("" : "+v"(iv2) : : "memory");
+    ray_setup(vv, a.G, iu, iv2, R2);
+    asm volatile("" : : "v"(R2.i0), "v"(R2.i1), "v"(R2.cb), "v"(R2.gb), "v"(R2.scale) : "memory");
+    const float4 c0 = s_stash[0][threadIdx.x], c1 = s_stash[1][threadIdx.x];
+    R1.ca = c0.x;
+    R1.ga = c0.y;
+    R1.cb = c0.z;
+    R1.gb = c0.w;
+    R1.m = __float_as_int(c1.x);
+    R1.i0 = __float_as_int(c1.y);
+    R1.i1 = __float_as_int(c1.z);
+    R1.scale = c1.w;
+    R1.ta = R1.m == 0 ? 1 : 0;
+    R1.tb = R1.m == 2 ? 1 : 2;
+  }
+  if (!valid1) R1.i1 = R1.i0;
+  if (!valid2) R2.i1 = R2.i0;
+  const bool has1 = R1.i1 > R1.i0, has2 = R2.i1 > R2.i0;
+  float acc1 = 0.0f, acc2 = 0.0f;
+  // a lane with one empty ray runs the other ray's coefficients in its place
+  // (same floors, so the shared load is that ray's own) and drops that sum
+  RaySetup P1 = R1, P2 = R2;
+  if (!has1) {
+    P1.cb = R2.cb;
+    P1.gb = R2.gb;
+  }
+  if (!has2) {
+    P2.cb = P1.cb;
+    P2.gb = P1.gb;
+  }
+  const bool any = has1 || has2;
+  const uint64_t hv = __ballot(any);
+  bool paired = false, swap = false;
+  int lm = 2, lo = 0, hi = 0, mid_lo = 0, mid_hi = 0;
+  float lca = 0.0f, lga = 0.0f;
+  if (hv != 0) {
+    const int leader = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)hv) - 1);
+    const RaySetup& L = has1 ? R1 : R2;
+    lm = __builtin_amdgcn_readlane(L.m, leader);
+    lca = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, L.ca), leader));
+    lga = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, L.ga), leader));
+    const bool off1 = has1 && (R1.m != lm || R1.ca != lca || R1.ga != lga);
+    const bool off2 = has2 && (R2.m != lm || R2.ca != lca || R2.ga != lga);
+    if (lm != 2 && __ballot(off1 || off2) == 0) {
+      const int i0 = min(has1 ? R1.i0 : 0x7fffffff, has2 ? R2.i0 : 0x7fffffff);
+      const int i1 = max(has1 ? R1.i1 : -1, has2 ? R2.i1 : -1);
+      const int j0 = max(has1 ? R1.i0 : -1, has2 ? R2.i0 : -1);
+      const int j1 = min(has1 ? R1.i1 : 0x7fffffff, has2 ? R2.i1 : 0x7fffffff);
+      lo = __builtin_amdgcn_readfirstlane(wave_min(any ? i0 : 0x7fffffff));
+      hi = __builtin_amdgcn_readfirstlane(wave_max(any ? i1 : -1));
+      mid_lo = __builtin_amdgcn_readfirstlane(wave_max(any ? j0 : -1));
+      mid_hi = __builtin_amdgcn_readfirstlane(wave_min(any ? j1 : 0x7fffffff));
+      // the difference of the two axis-2 coordinates is affine in the plane
+      // index, so its extremes over [lo, hi) are at the ends
+      const float fl = (float)lo, fh = (float)(hi - 1);
+      const float p1l = __builtin_fmaf(fl, P1.gb, P1.cb), p2l = __builtin_fmaf(fl, P2.gb, P2.cb);
+      const float p1h = __builtin_fmaf(fh, P1.gb, P1.cb), p2h = __builtin_fmaf(fh, P2.gb, P2.cb);
+      const float M = fmaxf(fmaxf(fmaxf(fabsf(p1l), fabsf(p2l)), fmaxf(fabsf(p1h), fabsf(p2h))),
+                            1.0f);
+      const float eps = M * 0x1p-20f;
+      const float dl = p2l - p1l, dh = p2h - p1h;
+      const bool same = P1.cb == P2.cb && P1.gb == P2.gb;
+      const bool pos = same || (dl >= eps && dl <= 1.0f - eps && dh >= eps && dh <= 1.0f - eps);
+      const bool neg = same || (-dl >= eps && -dl <= 1.0f - eps && -dh >= eps && -dh <= 1.0f - eps);
+      if (__ballot(!pos) == 0) {
+        paired = true;
+      } else if (__ballot(!neg) == 0) {
+        paired = true;
+        swap = true;
+      }
+    }
+  }
+  if (paired) {
+    // the ray with the lower axis-2 coordinate addresses the shared load
+    const RaySetup& A = swap ? P2 : P1;
+    const RaySetup& B = swap ? P1 : P2;
+    RaySetup Ac = A, Bc = B;
+    Ac.i0 = swap ? R2.i0 : R1.i0;
+    Ac.i1 = swap ? R2.i1 : R1.i1;
+    Bc.i0 = swap ? R1.i0 : R2.i0;
+    Bc.i1 = swap ? R1.i1 : R2.i1;
+    float sa, sb;
+    fwd_loop_rowuniform_pair<T, WF, GRP>(a, Ac, Bc, lm, lca, lga, lo, hi, mid_lo, mid_hi, sa, sb);
+    acc1 = has1 ? (swap ? sb : sa) : 0.0f;
+    acc2 = has2 ? (swap ? sa : sb) : 0.0f;
+    float* out = a.sino + ((size_t)view * a.n_u + iu) * a.n_v + iv;
+    if (valid1) out[0] = acc1 * R1.scale;
+    if (valid2) out[1] = acc2 * R2.scale;
+  } else {
+    // one ray set after the other; the second ray's setup is recomputed so
+    // that it does not stay live through the first one's loop
+    fwd_ray<T, WF, IDX64, GRP>(a, view, iu, iv, valid1);
+    fwd_ray<T, WF, IDX64, GRP>(a, view, iu, iv + 1, valid2);
+  }
+}
+
+template <typename T, int WF, bool IDX64, int GRP, bool PAIRS>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
   const int tu = t / a.tiles_v;
   const int tv = t - tu * a.tiles_v;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int k = a.tile_v_log2;
+  if constexpr (PAIRS && sizeof(T) == 2) {
+    if (k == 7) {
+      // 128 pixels along v per wavefront, two per lane; four columns
+      const int iv = (tv << 7) + 2 * lane;
+      const int iu = tu * 4 + wave;
+      const bool col = iu < a.n_u;
+      const bool v1 = col && iv < a.n_v, v2 = col && iv + 1 < a.n_v;
+      fwd_ray_pair<T, WF, IDX64, GRP>(a, view, col ? iu : 0, v1 ? iv : 0, v1, v2 && v1);
+      return;
+    }
+  }
   const int rows = 64 >> k;
   const int iv = (tv << k) + (lane & ((1 << k) - 1));
   const int iu = tu * (4 * rows) + wave * rows + (lane >> k);
@@ -445,8 +693,8 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
 // tile comes up for all the group's views in turn. Rays of nearby views cross
 // nearly the same voxels, so the workgroups resident on an XCD share their
 // volume reads in L2 instead of each view streaming the volume again.
-template <typename T, int WF, bool IDX64, int GRP>
-__global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
+template <typename T, int WF, bool IDX64, int GRP, bool PAIRS>
+__device__ __forceinline__ void fwd_block(const FwdArgs& a) {
   uint32_t b = blockIdx.x;
   if (a.remap) b = xcd_remap(b, gridDim.x);
   const uint32_t K = (uint32_t)a.view_group, tpv = (uint32_t)a.tiles_per_view;
@@ -455,7 +703,23 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
   const uint32_t v0 = grp * K;
   const uint32_t kg = min(K, (uint32_t)a.n_views - v0);  // views in this group
   const uint32_t t = r / kg;
-  fwd_tile<T, WF, IDX64, GRP>(a, (int)(v0 + (r - t * kg)), (int)t);
+  fwd_tile<T, WF, IDX64, GRP, PAIRS>(a, (int)(v0 + (r - t * kg)), (int)t);
+}
+
+template <typename T, int WF, bool IDX64, int GRP>
+__global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
+  fwd_block<T, WF, IDX64, GRP, false>(a);
+}
+
+#ifdef GJP_PAIR_WPE
+#define GJP_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(GJP_PAIR_WPE)))
+#else
+#define GJP_PAIR_ATTR
+#endif
+// Two rays per lane (16-bit storage, 128-wide tiles).
+template <typename T, int WF, bool IDX64, int GRP>
+__global__ __launch_bounds__(256) GJP_PAIR_ATTR void fwd_pair_kernel(const FwdArgs a) {
+  fwd_block<T, WF, IDX64, GRP, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1087,7 +1351,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void b
     const uint2 it = items[item];
     const int inst = (int)(it.x & 0xfffu);
     const int view = (int)(it.x >> 12);
-    fwd_tile<T, WF, IDX64, kBatchRuGroup>(insts[inst].a, view, (int)it.y);
+    fwd_tile<T, WF, IDX64, kBatchRuGroup, false>(insts[inst].a, view, (int)it.y);
   }
 }
 
@@ -1173,19 +1437,47 @@ int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int
   return check_launch("pad kernel");
 }
 
+template <typename T, int WF, bool PAIRS>
+static void launch_fwd_g(const FwdArgs& a, bool idx64, unsigned grid, hipStream_t s) {
+  if constexpr (PAIRS) {
+    if (a.ru_group == 2) {
+      if (idx64)
+        fwd_pair_kernel<T, WF, true, 2><<<grid, 256, 0, s>>>(a);
+      else
+        fwd_pair_kernel<T, WF, false, 2><<<grid, 256, 0, s>>>(a);
+    } else {
+      if (idx64)
+        fwd_pair_kernel<T, WF, true, 4><<<grid, 256, 0, s>>>(a);
+      else
+        fwd_pair_kernel<T, WF, false, 4><<<grid, 256, 0, s>>>(a);
+    }
+  } else {
+    if (a.ru_group == 2) {
+      if (idx64)
+        fwd_kernel<T, WF, true, 2><<<grid, 256, 0, s>>>(a);
+      else
+        fwd_kernel<T, WF, false, 2><<<grid, 256, 0, s>>>(a);
+    } else {
+      if (idx64)
+        fwd_kernel<T, WF, true, 4><<<grid, 256, 0, s>>>(a);
+      else
+        fwd_kernel<T, WF, false, 4><<<grid, 256, 0, s>>>(a);
+    }
+  }
+}
+
+// Two rays per lane (tile_v_log2 == 7, 16-bit storage only) is a separate
+// kernel: its second ray setup raises the register count, which the one-ray
+// tiles should not pay in occupancy.
 template <typename T, int WF>
 static void launch_fwd_t(const FwdArgs& a, bool idx64, unsigned grid, hipStream_t s) {
-  if (a.ru_group == 2) {
-    if (idx64)
-      fwd_kernel<T, WF, true, 2><<<grid, 256, 0, s>>>(a);
-    else
-      fwd_kernel<T, WF, false, 2><<<grid, 256, 0, s>>>(a);
-  } else {
-    if (idx64)
-      fwd_kernel<T, WF, true, 4><<<grid, 256, 0, s>>>(a);
-    else
-      fwd_kernel<T, WF, false, 4><<<grid, 256, 0, s>>>(a);
+  if constexpr (sizeof(T) == 2) {
+    if (a.tile_v_log2 == 7) {
+      launch_fwd_g<T, WF, true>(a, idx64, grid, s);
+      return;
+    }
   }
+  launch_fwd_g<T, WF, false>(a, idx64, grid, s);
 }
 
 int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,

@@ -87,6 +87,9 @@ def test_error_paths_without_gpu(gjp):
     for args in ((0, 48, 8, 4), (0, 64, 0, 4), (0, 64, 65, 4), (0, 64, 8, 3), (5, 64, 8, 4)):
         assert L.gjp_set_forward_tile(h, *args) == _lib.GJP_EINVAL, args
     assert L.gjp_set_forward_tile(None, 0, 64, 8, 4) == _lib.GJP_EINVAL
+    # two rays per lane (128-wide tiles) exist for 16-bit storage only
+    assert L.gjp_set_forward_tile(h, 1, 128, 8, 2) == _lib.GJP_OK
+    assert L.gjp_set_forward_tile(h, 0, 128, 8, 2) == _lib.GJP_EINVAL
     assert L.gjp_forward_project_batched(0, None, None, None, None, None) == _lib.GJP_EINVAL
     cnt = ctypes.c_uint64()
     assert L.gjp_count_samples(None, ctypes.byref(cnt)) == _lib.GJP_EINVAL

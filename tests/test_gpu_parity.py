@@ -267,7 +267,8 @@ def test_circular_tiles_bitwise_and_adjoint(gjp, oracle_mod, beam):
     configs = [(64, 8, 4), (64, 8, 2), (64, 1, 4), (64, 16, 2), (32, 8, 4), (16, 3, 2)]
     for dt in (torch.float32, torch.bfloat16):
         got = []
-        for tv, vg, lg in configs:
+        pairs = [(128, 8, 2), (128, 1, 4)] if dt != torch.float32 else []
+        for tv, vg, lg in configs + pairs:
             gjp.set_forward_tile(G, dt, tv, vg, lg)
             note(f"circular {beam} tile {tv} views {vg} loads {lg} {dt}")
             got.append(gjp.forward(x.to(dt), G))
@@ -367,3 +368,50 @@ def test_naive_forward_16bit(gjp, oracle_mod, dtype):
     og = oracle_mod.geometry_for(cfg)
     assert rel_l2(y, oracle_mod.forward(og, v16.float().cpu().numpy())) <= TOL32
     assert rel_l2(y, oracle_mod.forward(og, vol)) <= TOL16
+
+
+# ---------------------------------------------------------------------------
+# two rays per lane (16-bit storage, 128-wide tiles): the shared load applies
+# when the two rays' axis-2 coordinates stay within a voxel; otherwise each ray
+# runs alone. Either way the sums equal the one-ray tiles' bit for bit.
+# ---------------------------------------------------------------------------
+def _flip_v(views, n_v):
+    out = views.copy()
+    out[:, 3:6] = views[:, 3:6] + (n_v - 1) * views[:, 9:12]
+    out[:, 9:12] = -views[:, 9:12]
+    return out
+
+
+@pytest.mark.parametrize("case", ["cone", "flipped", "coarse", "parallel", "clipped"])
+def test_two_rays_per_lane_bitwise(gjp, oracle_mod, case):
+    import torch
+    dev = cuda()
+    shape = (46, 40, 66)
+    n_views, n_u, n_v = 10, 53, 141  # odd n_v: the last lane's second ray is off the detector
+    clip = case == "clipped"
+    if case == "parallel":
+        views = gjp.views_parallel(n_views, 0.9, 0.8, n_u, n_v)
+        beam = "parallel"
+    else:
+        # coarse: v pitch of about 2.4 voxels at the axis, so the rays of a
+        # lane drift more than a voxel apart and the path falls back
+        pv = 3.6 if case == "coarse" else 1.1
+        views = gjp.views_circular_cone(n_views, 160.0, 240.0, 1.2, pv, n_u, n_v)
+        beam = "cone"
+    if case == "flipped":
+        views = _flip_v(views, n_v)
+    G = gjp.Geometry(shape, views, n_u, n_v, beam=beam, clip_cylinder=clip)
+    vol = workloads.rasterize(workloads.random_ellipsoids(121, shape), shape)
+    for dt in (torch.bfloat16, torch.float16):
+        x = _to_dev(vol, dev).to(dt)
+        gjp.set_forward_tile(G, dt, 64, 8, 4)
+        note(f"two rays per lane {case} {dt}: reference tile")
+        ref = gjp.forward(x, G)
+        for vg, lg in ((8, 2), (1, 4), (16, 2)):
+            gjp.set_forward_tile(G, dt, 128, vg, lg)
+            note(f"two rays per lane {case} {dt}: views {vg} loads {lg}")
+            assert torch.equal(gjp.forward(x, G), ref)
+    og = _oracle_geom(oracle_mod, G)
+    rounded = _to_dev(vol, dev).to(torch.float16).float().cpu().numpy()
+    y = gjp.forward(_to_dev(vol, dev).to(torch.float16), G).cpu().numpy()
+    assert rel_l2(y, oracle_mod.forward(og, rounded)) <= TOL32
