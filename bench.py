@@ -282,6 +282,39 @@ def bench_sart(args, torch, gjp, workloads, dev):
     print(json.dumps(out), flush=True)
 
 
+def forward_dtypes_512(args, torch, gjp, workloads, dev):
+    """FP32, BF16 and FP16 forwards at 512^3 / 720 views / 768^2 (each after
+    its own autotuning, untimed), two timed launches each: the storage-type
+    comparison at the size the 16-bit target refers to."""
+    cfg = workloads.config("c3")
+    G = gjp.Geometry.from_config(cfg)
+    S = G.count_samples()
+    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    out = {"workload": f"{cfg.name}: {cfg.shape[0]}^3, {cfg.n_views} views, "
+                       f"{cfg.n_u}x{cfg.n_v} detector", "ray_samples_per_pass": S}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
+        xv = x.to(dt)
+        y = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
+        tile = gjp.autotune(xv, G, y) if not args.no_autotune else None
+        gjp.forward(xv, G, y)
+        torch.cuda.synchronize()
+        gjp.timing_reset()
+        gjp.timing_enable(True)
+        for _ in range(2):
+            gjp.forward(xv, G, y)
+        torch.cuda.synchronize()
+        gjp.timing_enable(False)
+        ms, n = gjp.timing_read("forward")
+        out[name] = {"ms": ms / n, "ray_samples_per_s": S / (ms / n * 1e-3), "tile_v": tile}
+        log(f"512^3 forward {name}: {ms / n:.2f} ms (tile_v {tile})")
+        del xv, y
+    out["speedup_bf16_vs_f32"] = out["f32"]["ms"] / out["bf16"]["ms"]
+    out["speedup_f16_vs_f32"] = out["f32"]["ms"] / out["f16"]["ms"]
+    del x
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,14 +325,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the forward autotuning that precedes the warm-up (untimed)")
+    ap.add_argument("--no-512", action="store_true",
+                    help="skip the FP32 / BF16 / FP16 forward comparison at 512^3 (untimed "
+                         "by the step clock; reported under kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy before the steps (untimed), a "
                          "reference kernel of known traffic for hardware byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: every box in this setup has one GPU and the "
-              "projector is benchmarked on one GPU's share of the work (--gpus 1).",
+        print("bench.py measures one GPU only (--gpus 1): the projector is benchmarked on one "
+              "GPU's share of the work; runs over several GPUs are not supported.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -433,6 +469,8 @@ def main():
         "speedup_f32_vs_naive_f32": naive["f32"]["ms"] / per_dtype["f32"]["ms"],
         "speedup_bf16_vs_naive_f32": naive["f32"]["ms"] / per_dtype["bf16"]["ms"],
     }
+    if not args.no_512:
+        kernels["forward_dtypes_512"] = forward_dtypes_512(args, torch, gjp, workloads, dev)
     # dominant kernel of the step
     fwd_step_ms = fwd_ms / args.steps
     if gat_ms >= fwd_ms / 3.0:

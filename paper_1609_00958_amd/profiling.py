@@ -29,6 +29,8 @@ SHORT = (
     ("naive_fwd_kernel<float", "forward_naive_f32"),
     ("naive_fwd_kernel<gjp::bf16_t", "forward_naive_bf16"),
     ("naive_fwd_kernel<gjp::f16_t", "forward_naive_f16"),
+    ("fwd_pair_kernel<gjp::bf16_t", "forward_bf16_pairs"),
+    ("fwd_pair_kernel<gjp::f16_t", "forward_f16_pairs"),
     ("batched_fwd_kernel", "batched"),
     ("batched_pad_kernel", "batched_pad"),
     ("fwd_kernel<float", "forward_f32"),

@@ -76,6 +76,8 @@ def test_profile_kernel_names():
         "void gjp::naive_fwd_kernel<float, 0>(gjp::GridGeom, double const*)": "forward_naive_f32",
         "void gjp::naive_fwd_kernel<gjp::f16_t, 1>(gjp::GridGeom)": "forward_naive_f16",
         "void gjp::batched_pad_kernel(gjp::BatchInst const*)": "batched_pad",
+        "void gjp::fwd_pair_kernel<gjp::f16_t, 0, false, 2>(gjp::FwdArgs)": "forward_f16_pairs",
+        "void gjp::fwd_kernel<gjp::f16_t, 0, false, 4>(gjp::FwdArgs)": "forward_f16",
         "void gjp::pad_kernel<unsigned int>(unsigned int const*)": "pad",
         "void gjp::adj_gather_sep_kernel<0>(gjp::GridGeom)": "adjoint_gather",
         "elementwise_kernel<...>": None,
