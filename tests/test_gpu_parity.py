@@ -247,6 +247,34 @@ def test_forward_64bit_offsets(gjp, oracle_mod, dtype, shape):
         assert rel_l2(got, want) <= TOL32
 
 
+def test_two_rays_per_lane_64bit_offsets(gjp, oracle_mod):
+    """Circular trajectory over planes beyond 24-bit byte strides (the 64-bit
+    per-lane fallback is compiled into the two-ray kernel as well)."""
+    import torch
+    dev = cuda()
+    shape = (4, 2050, 2050)
+    assert (shape[1] + 2) * (shape[2] + 2) * 2 >= (1 << 23)
+    n_views, n_u, n_v = 8, 40, 130
+    G = gjp.Geometry.circular_cone(shape, n_views, n_u, n_v, 6000.0, 9000.0, 40.0, 1.2)
+    og = _oracle_geom(oracle_mod, G)
+    # a smooth phantom: rays here run up to 2050 planes at coordinates in the
+    # thousands, where uncorrelated voxel noise would turn single-precision
+    # coordinate rounding into more than the tolerance
+    vol = workloads.rasterize(workloads.random_ellipsoids(104, shape), shape)
+    x = _to_dev(vol, dev).to(torch.bfloat16)
+    vol = x.float().cpu().numpy()
+    gjp.set_forward_tile(G, torch.bfloat16, 64, 8, 4)
+    note("two rays per lane, 64-bit strides: reference tile")
+    ref = gjp.forward(x, G)
+    gjp.set_forward_tile(G, torch.bfloat16, 128, 8, 2)
+    note("two rays per lane, 64-bit strides: 128-wide tile")
+    y = gjp.forward(x, G)
+    assert torch.equal(y, ref)
+    rays = workloads.sample_rays(105, 1500, n_views, n_u, n_v)
+    got = y.cpu().numpy()[rays[:, 0], rays[:, 1], rays[:, 2]]
+    assert rel_l2(got, oracle_mod.forward_rays(og, vol, rays)) <= TOL32
+
+
 @pytest.mark.parametrize("beam", ["cone", "parallel"])
 def test_circular_tiles_bitwise_and_adjoint(gjp, oracle_mod, beam):
     """Circular trajectories: the 64-wide tile takes the row-uniform sampling
