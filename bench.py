@@ -282,6 +282,63 @@ def bench_sart(args, torch, gjp, workloads, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_dtypes_512(args, torch, gjp, workloads, dev):
+    """FP32, BF16 and FP16 storage at 512^3 / 720 views / 768^2: each dtype
+    autotuned first (untimed); a step is one forward of each."""
+    cfg = workloads.config("c3")
+    G = gjp.Geometry.from_config(cfg)
+    S = G.count_samples()
+    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    vols = [x, x.to(torch.bfloat16), x.to(torch.float16)]
+    y = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
+    tiles = [None if args.no_autotune else gjp.autotune(v, G, y) for v in vols]
+    log(f"autotuned tile_v f32 / bf16 / f16: {tiles}")
+    for _ in range(args.warmup):
+        for v in vols:
+            gjp.forward(v, G, y)
+    torch.cuda.synchronize()
+    gjp.timing_reset()
+    gjp.timing_enable(True)
+    t0 = time.perf_counter()
+    per = [0.0, 0.0, 0.0]
+    for _ in range(args.steps):
+        for k, v in enumerate(vols):
+            gjp.forward(v, G, y)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gjp.timing_enable(False)
+    # per-dtype kernel times: one more launch of each, timed alone
+    for k, v in enumerate(vols):
+        gjp.timing_reset()
+        gjp.timing_enable(True)
+        gjp.forward(v, G, y)
+        torch.cuda.synchronize()
+        gjp.timing_enable(False)
+        ms, n = gjp.timing_read("forward")
+        per[k] = ms / n
+    out = {
+        "metric": "GJP forward ray-samples/s by volume storage type (FP32, BF16, FP16)",
+        "value": 3 * S / (elapsed / args.steps),
+        "unit": "ray-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/bf16/f16 storage, f32 math",
+        "data": "synthetic",
+        "config": {"workload": "dtypes512: 512^3 Shepp-Logan-type volume, 720 cone-beam views, "
+                               "768x768 detector; step = FP32 + BF16 + FP16 forward",
+                   "ray_samples_per_pass": S, "tile_v": tiles,
+                   "forward_ms": {"f32": per[0], "bf16": per[1], "f16": per[2]},
+                   "speedup_bf16_vs_f32": per[0] / per[1],
+                   "speedup_f16_vs_f32": per[0] / per[2]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def forward_dtypes_512(args, torch, gjp, workloads, dev):
     """FP32, BF16 and FP16 forwards at 512^3 / 720 views / 768^2 (each after
     its own autotuning, untimed), two timed launches each: the storage-type
@@ -351,6 +408,8 @@ def main():
         return bench_t1(args, torch, gjp, workloads, dev)
     if args.workload == "sart":
         return bench_sart(args, torch, gjp, workloads, dev)
+    if args.workload == "dtypes512":
+        return bench_dtypes_512(args, torch, gjp, workloads, dev)
     cfg = workloads.config(args.workload)
     log(f"workload {cfg.name}: {cfg.shape} grid, {cfg.n_views} views, {cfg.n_u}x{cfg.n_v}")
     t0 = time.perf_counter()

@@ -445,6 +445,24 @@ __device__ __forceinline__ Triple buf_triple(__amdgpu_buffer_rsrc_t r, uint32_t 
   return {v.x, v.y, v.z};
 }
 
+// The two rays' neighbour quads from three consecutive pair elements: the
+// first ray's at elements 0, 1; the second's at 0, 1 or, one floor up, 1, 2.
+// FP16 selects whole elements (the mixed-precision FMAs widen them); BF16
+// widens the three elements once and selects the values.
+__device__ __forceinline__ void pair_quads(const Triple& t, bool up, const f16_t* tag, Quad& q1,
+                                           Quad& q2) {
+  q1 = widen4(u2v{t.e0, t.e1}, tag);
+  q2 = widen4(u2v{up ? t.e1 : t.e0, up ? t.e2 : t.e1}, tag);
+}
+__device__ __forceinline__ void pair_quads(const Triple& t, bool up, const bf16_t*, Quad& q1,
+                                           Quad& q2) {
+  const float l0 = __uint_as_float(t.e0 << 16), h0 = __uint_as_float(t.e0 & 0xffff0000u);
+  const float l1 = __uint_as_float(t.e1 << 16), h1 = __uint_as_float(t.e1 & 0xffff0000u);
+  const float l2 = __uint_as_float(t.e2 << 16), h2 = __uint_as_float(t.e2 & 0xffff0000u);
+  q1 = {l0, h0, l1, h1};
+  q2 = {up ? l1 : l0, up ? h1 : h0, up ? l2 : l1, up ? h2 : h1};
+}
+
 // Row-uniform loop over two rays per lane for 16-bit storage. The two rays of
 // a lane share the driving axis and the in-plane coefficients with every
 // other ray of the wavefront (one detector column), so on each plane they
@@ -522,10 +540,10 @@ __device__ __forceinline__ void fwd_loop_rowuniform_pair(const FwdArgs& a, const
           wfa2 = in2 ? wfa2 : 0.0f;
           wca2 = in2 ? wca2 : 0.0f;
         }
-        const u2v d1 = {u[k].e0, u[k].e1};
-        const u2v d2 = {up[k] ? u[k].e1 : u[k].e0, up[k] ? u[k].e2 : u[k].e1};
-        acc1 = accumulate4(acc1, wfa1, wca1, wfb1[k], wcb1[k], widen4(d1, (const T*)nullptr));
-        acc2 = accumulate4(acc2, wfa2, wca2, wfb2[k], wcb2[k], widen4(d2, (const T*)nullptr));
+        Quad q1, q2;
+        pair_quads(u[k], up[k], (const T*)nullptr, q1, q2);
+        acc1 = accumulate4(acc1, wfa1, wca1, wfb1[k], wcb1[k], q1);
+        acc2 = accumulate4(acc2, wfa2, wca2, wfb2[k], wcb2[k], q2);
       }
     };
     using yes = std::true_type;

@@ -110,6 +110,27 @@ def scaled_traffic(pmc_dir: str, ref_bytes: float = float(1 << 30)):
     return {k: sum(v) / len(v) for k, v in acc.items()}, scale
 
 
+def kernel_stats_last(trace_dir: str, n: int):
+    """Per-kernel average over the last n dispatches of each kernel (from the
+    per-dispatch trace), so that set-up launches such as autotuning trials
+    before the timed steps do not enter the averages."""
+    runs = collections.defaultdict(list)
+    with open(_one(trace_dir, "kernel_trace.csv")) as f:
+        for row in csv.DictReader(f):
+            s = short_name(row["Kernel_Name"])
+            if s is None:
+                continue
+            t0, t1 = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+            runs[s].append((t0, t1 - t0))
+    out = {}
+    for s, v in runs.items():
+        v.sort()
+        last = v[-n:]
+        total = float(sum(d for _, d in last))
+        out[s] = {"calls": len(last), "total_ns": total, "avg_ms": total / len(last) / 1e6}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -119,15 +140,19 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--out-md", required=True)
     ap.add_argument("--out-json")
+    ap.add_argument("--last", type=int, default=0,
+                    help="average only the last N dispatches of each kernel")
     a = ap.parse_args()
-    stats = kernel_stats(a.trace)
+    stats = kernel_stats_last(a.trace, a.last) if a.last > 0 else kernel_stats(a.trace)
     fetch = write = None
     fscale = wscale = None
     if a.fetch and a.write:
         fetch, fscale = scaled_traffic(a.fetch)
         write, wscale = scaled_traffic(a.write)
+    head = "launches" if a.last <= 0 else f"launches (last {a.last})"
     lines = [f"# {a.label}", "", "Command(s):", "", "```", a.command, "```", "",
-             "| kernel | launches | avg ms / launch | HBM fetch GB / launch | HBM write GB / launch |",
+             f"| kernel | {head} | avg ms / launch | HBM fetch GB / launch | "
+             "HBM write GB / launch |",
              "|---|---|---|---|---|"]
     for k in sorted(stats, key=lambda k: -stats[k]["total_ns"]):
         f = f"{fetch[k] / 1e9:.3f}" if fetch and k in fetch else "-"

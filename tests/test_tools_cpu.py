@@ -67,6 +67,25 @@ def test_profile_summary(tmp_path):
     assert data["kernels"]["forward_f32"]["fetch_bytes_per_launch"] == 1000.0 * 1024 * 2.0
 
 
+
+def test_profile_last_dispatches(tmp_path):
+    """--last N averages the final N dispatches of each kernel (after set-up
+    launches such as autotuning trials)."""
+    from paper_1609_00958_amd import profiling
+    trace = tmp_path / "trace"
+    trace.mkdir()
+    fwd = "void gjp::fwd_pair_kernel<gjp::bf16_t, 0, false, 2>(gjp::FwdArgs)"
+    rows = [[i, fwd, 1000 * i, 1000 * i + d] for i, d in enumerate([900, 50, 70, 100, 100])]
+    rows.append([9, "elementwise_kernel<...>", 0, 5])
+    _write_csv(trace / "x_kernel_trace.csv",
+               ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
+    stats = profiling.kernel_stats_last(str(trace), 2)
+    assert list(stats) == ["forward_bf16_pairs"]
+    assert stats["forward_bf16_pairs"]["calls"] == 2
+    assert abs(stats["forward_bf16_pairs"]["avg_ms"] - 100e-6) < 1e-12
+    assert profiling.kernel_stats_last(str(trace), 10)["forward_bf16_pairs"]["calls"] == 5
+
+
 def test_profile_kernel_names():
     from paper_1609_00958_amd import profiling
     want = {
