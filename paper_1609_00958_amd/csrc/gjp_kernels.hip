@@ -1056,10 +1056,12 @@ __global__ __launch_bounds__(256) void adj_splat_kernel(
 // ---------------------------------------------------------------------------
 
 // Weights of one sample for the voxels z and z + 1 (zero unless the sample's
-// floor or floor + 1 is one of them). Linear: the tent 1 - |p - z| on the
-// clamped coordinate, which reproduces the forward's 1 - d and d (differences
-// of nearby floats are exact); other weights: the forward's floor and
-// complementary weights, selected by the floor's position.
+// floor or floor + 1 is one of them). Linear, on the clamped coordinate p with
+// s = p - z: voxel z takes the tent 1 - |s|, voxel z + 1 the tent
+// min(s, 2 - s) cut at 0. These reproduce the forward's 1 - d and d bit for
+// bit: p - z, p - floor(p) and 2 - s are exact differences of nearby floats,
+// and 1 - (z - p) equals p - (z - 1) exactly. Other weights: the forward's
+// floor and complementary weights, selected by the floor's position.
 template <int WF>
 __device__ __forceinline__ void pair_weights(float fplane, float g, float c, float hz, float fz,
                                              int z, float& b0, float& b1) {
@@ -1067,10 +1069,10 @@ __device__ __forceinline__ void pair_weights(float fplane, float g, float c, flo
     float p = __builtin_fmaf(fplane, g, c);
     p = __builtin_amdgcn_fmed3f(p, -1.0f, hz);
     const float s0 = p - fz;
-    const float s1 = s0 - 1.0f;
     // clamp to [0, 1] (one instruction with the clamp modifier); 1 - |s| <= 1
     b0 = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(s0), 0.0f, 1.0f);
-    b1 = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(s1), 0.0f, 1.0f);
+    // min(s, 2 - s) <= 1, so only the cut at 0 remains: the median of the three
+    b1 = __builtin_amdgcn_fmed3f(s0, 2.0f - s0, 0.0f);
   } else {
     int ib;
     float wfb, wcb;
