@@ -288,7 +288,12 @@ def bench_dtypes_512(args, torch, gjp, workloads, dev):
     cfg = workloads.config("c3")
     G = gjp.Geometry.from_config(cfg)
     S = G.count_samples()
-    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    if args.volume == "uniform":
+        # the kernels' work does not depend on voxel values; one fill kernel
+        # instead of the phantom's many small ones (for counter collection)
+        x = torch.rand(cfg.shape, device=dev, generator=torch.Generator(device=dev).manual_seed(3))
+    else:
+        x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
     vols = [x, x.to(torch.bfloat16), x.to(torch.float16)]
     y = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
     tiles = [None if args.no_autotune else gjp.autotune(v, G, y) for v in vols]
@@ -329,8 +334,9 @@ def bench_dtypes_512(args, torch, gjp, workloads, dev):
         "vs_baseline": None,
         "dtype": "f32/bf16/f16 storage, f32 math",
         "data": "synthetic",
-        "config": {"workload": "dtypes512: 512^3 Shepp-Logan-type volume, 720 cone-beam views, "
-                               "768x768 detector; step = FP32 + BF16 + FP16 forward",
+        "config": {"workload": f"dtypes512: 512^3 {'uniform random' if args.volume == 'uniform' else 'Shepp-Logan-type'} "
+                               "volume, 720 cone-beam views, 768x768 detector; step = FP32 + "
+                               "BF16 + FP16 forward",
                    "ray_samples_per_pass": S, "tile_v": tiles,
                    "forward_ms": {"f32": per[0], "bf16": per[1], "f16": per[2]},
                    "speedup_bf16_vs_f32": per[0] / per[1],
@@ -382,6 +388,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the forward autotuning that precedes the warm-up (untimed)")
+    ap.add_argument("--volume", choices=("phantom", "uniform"), default="phantom",
+                    help="dtypes512 only: the Shepp-Logan-type phantom or a uniform random "
+                         "volume (same work; fewer set-up kernels under a profiler)")
     ap.add_argument("--no-512", action="store_true",
                     help="skip the FP32 / BF16 / FP16 forward comparison at 512^3 (untimed "
                          "by the step clock; reported under kernels)")

@@ -131,6 +131,65 @@ def kernel_stats_last(trace_dir: str, n: int):
     return out
 
 
+def counters_last(dirs, n: int):
+    """{kernel: {counter: average over the kernel's last n dispatches}} from
+    one or more --pmc runs of the same program (each run one pass)."""
+    out = collections.defaultdict(dict)
+    for d in dirs:
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        names = {}
+        with open(_one(d, "counter_collection.csv")) as f:
+            for row in csv.DictReader(f):
+                s = short_name(row["Kernel_Name"])
+                if s is None:
+                    continue
+                disp = int(row["Dispatch_Id"])
+                names[disp] = s
+                per[disp][row["Counter_Name"]] += float(row["Counter_Value"])
+        by_kernel = collections.defaultdict(list)
+        for disp in sorted(per):
+            by_kernel[names[disp]].append(per[disp])
+        for k, runs in by_kernel.items():
+            last = runs[-n:]
+            for c in last[0]:
+                out[k][c] = sum(r.get(c, 0.0) for r in last) / len(last)
+    return out
+
+
+# Derived figures of the counter table: (label, function of the counters).
+# GRBM_GUI_ACTIVE sums the eight XCDs' clocks; per-CU unit counters sum 256 CUs.
+DERIVED = (
+    ("VALU instr / wave", lambda c: c["SQ_INSTS_VALU"] / c["SQ_WAVES"]),
+    ("load instr / wave", lambda c: c["SQ_INSTS_VMEM_RD"] / c["SQ_WAVES"]),
+    ("LDS instr / wave", lambda c: c["SQ_INSTS_LDS"] / c["SQ_WAVES"]),
+    ("VALU issue (2 cycles / wave instr)",
+     lambda c: 2.0 * c["SQ_INSTS_VALU"] / (1024.0 * c["GRBM_GUI_ACTIVE"] / 8.0)),
+    ("address unit busy (TA)", lambda c: 8.0 * c["TA_TA_BUSY_sum"] / c["GRBM_GUI_ACTIVE"] / 256.0),
+    ("data unit busy (TD)", lambda c: 8.0 * c["TD_TD_BUSY_sum"] / c["GRBM_GUI_ACTIVE"] / 256.0),
+    ("TA cycles / load instr", lambda c: c["TA_TA_BUSY_sum"] / c["SQ_INSTS_VMEM_RD"]),
+    ("L1 tag accesses / load instr",
+     lambda c: c["TCP_TOTAL_CACHE_ACCESSES_sum"] / c["SQ_INSTS_VMEM_RD"]),
+    ("L1 -> L2 requests / L1 access",
+     lambda c: c["TCP_TCC_READ_REQ_sum"] / c["TCP_TOTAL_CACHE_ACCESSES_sum"]),
+    ("L2 hit rate", lambda c: c["TCC_HIT_sum"] / (c["TCC_HIT_sum"] + c["TCC_MISS_sum"])),
+)
+
+
+def counter_table(stats):
+    kernels = sorted(stats)
+    lines = ["| figure | " + " | ".join(kernels) + " |",
+             "|---|" + "---|" * len(kernels)]
+    for label, fn in DERIVED:
+        cells = []
+        for k in kernels:
+            try:
+                cells.append(f"{fn(stats[k]):.3g}")
+            except (KeyError, ZeroDivisionError):
+                cells.append("-")
+        lines.append(f"| {label} | " + " | ".join(cells) + " |")
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -142,6 +201,8 @@ def main():
     ap.add_argument("--out-json")
     ap.add_argument("--last", type=int, default=0,
                     help="average only the last N dispatches of each kernel")
+    ap.add_argument("--counters", nargs="*", default=[],
+                    help="--pmc run directories: adds a table of derived counter figures")
     a = ap.parse_args()
     stats = kernel_stats_last(a.trace, a.last) if a.last > 0 else kernel_stats(a.trace)
     fetch = write = None
@@ -161,6 +222,9 @@ def main():
     if fscale:
         lines += ["", f"Byte counters scaled by the 1 GiB copy reference: FETCH_SIZE x {fscale:.3f}, "
                       f"WRITE_SIZE x {wscale:.3f}."]
+    if a.counters:
+        lines += ["", "Counters (last " + str(max(a.last, 1)) + " dispatches of each kernel):", ""]
+        lines += counter_table(counters_last(a.counters, max(a.last, 1)))
     lines += ["", f"Kernel source sha256: `{source_hash()}`", ""]
     with open(a.out_md, "w") as f:
         f.write("\n".join(lines))

@@ -103,3 +103,28 @@ def test_profile_kernel_names():
     }
     for name, short in want.items():
         assert profiling.short_name(name) == short, name
+
+
+def test_profile_counter_table(tmp_path):
+    from paper_1609_00958_amd import profiling
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    k = "void gjp::fwd_kernel<float, 0, false, 4>(gjp::FwdArgs)"
+    d1, d2 = tmp_path / "a", tmp_path / "b"
+    d1.mkdir()
+    d2.mkdir()
+    # two dispatches; the last one counts: 100 waves, 5000 VALU, 50 loads
+    _write_csv(d1 / "x_counter_collection.csv", hdr, [
+        [1, k, "SQ_WAVES", 1.0], [1, k, "SQ_INSTS_VALU", 1.0], [1, k, "SQ_INSTS_VMEM_RD", 1.0],
+        [2, k, "SQ_WAVES", 60.0], [2, k, "SQ_WAVES", 40.0], [2, k, "SQ_INSTS_VALU", 5000.0],
+        [2, k, "SQ_INSTS_VMEM_RD", 50.0]])
+    _write_csv(d2 / "x_counter_collection.csv", hdr, [
+        [7, k, "TA_TA_BUSY_sum", 8.0e5], [7, k, "GRBM_GUI_ACTIVE", 8000.0]])
+    st = profiling.counters_last([str(d1), str(d2)], 1)
+    assert st["forward_f32"]["SQ_WAVES"] == 100.0
+    rows = {r.split("|")[1].strip(): r.split("|")[2].strip()
+            for r in profiling.counter_table(st)[2:]}
+    assert rows["VALU instr / wave"] == "50"
+    assert rows["load instr / wave"] == "0.5"
+    # TA busy per CU: 8 * 8e5 / 8000 / 256 = 3.125 (a synthetic ratio)
+    assert rows["address unit busy (TA)"] == "3.12"
+    assert rows["L2 hit rate"] == "-"
