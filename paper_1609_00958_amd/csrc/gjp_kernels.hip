@@ -522,11 +522,12 @@ __device__ __forceinline__ void fwd_loop_rowuniform_pair(const FwdArgs& a, const
       for (int k = 0; k < NP; ++k) q[k] = slots[j + k];
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
-        int ib1, ib2;
-        sample_axis<WF>(q[k].w, R1.gb, R1.cb, hib, ib1, wfb1[k], wcb1[k]);
-        sample_axis<WF>(q[k].w, R2.gb, R2.cb, hib, ib2, wfb2[k], wcb2[k]);
-        up[k] = ib2 != ib1;
-        const uint32_t vo = (uint32_t)(ib1 + 1) * pe + __float_as_uint(q[k].x);
+        // floors compared as floats: only the first ray's becomes an address
+        float f1, f2;
+        sample_axis_floor<WF>(q[k].w, R1.gb, R1.cb, hib, f1, wfb1[k], wcb1[k]);
+        sample_axis_floor<WF>(q[k].w, R2.gb, R2.cb, hib, f2, wfb2[k], wcb2[k]);
+        up[k] = f2 != f1;
+        const uint32_t vo = (uint32_t)((int)f1 + 1) * pe + __float_as_uint(q[k].x);
         u[k] = buf_triple(rs, vo);
       }
 #pragma unroll

@@ -234,19 +234,27 @@ __device__ __forceinline__ float weight_fn(float d) {
 // (Eqs. 10-11). The clamp only acts where single-precision rounding leaves a
 // coordinate outside the double-precision sample range.
 template <int WF>
-__device__ __forceinline__ void sample_axis(float fi, float g, float c, float hi, int& i_fl,
-                                            float& w_fl, float& w_cl) {
+__device__ __forceinline__ void sample_axis_floor(float fi, float g, float c, float hi, float& f,
+                                                  float& w_fl, float& w_cl) {
   float p = __builtin_fmaf(fi, g, c);
   p = __builtin_amdgcn_fmed3f(p, -1.0f, hi);
-  const float f = __builtin_floorf(p);
+  f = __builtin_floorf(p);
   const float d = p - f;
-  i_fl = (int)f;
   w_fl = weight_fn<WF>(d);
   // complementary weight (Eq. 12); for the linear weight 1 - (1 - d) is d
   if constexpr (WF == W_LINEAR)
     w_cl = d;
   else
     w_cl = 1.0f - w_fl;
+}
+
+// The same with the floor as an integer.
+template <int WF>
+__device__ __forceinline__ void sample_axis(float fi, float g, float c, float hi, int& i_fl,
+                                            float& w_fl, float& w_cl) {
+  float f;
+  sample_axis_floor<WF>(fi, g, c, hi, f, w_fl, w_cl);
+  i_fl = (int)f;
 }
 
 }  // namespace gjp
