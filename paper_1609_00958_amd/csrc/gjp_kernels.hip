@@ -1245,12 +1245,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
           iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
           // an interval of length L holds at most floor(L) + 1 integers; the
-          // longest window of the wavefront is at one of its ends
-          float lo_a, hi_a, lo_b, hi_b;
-          const float zw = (float)(2 * zb * 64);
-          window(zw, lo_a, hi_a);
-          window(zw + 126.0f, lo_b, hi_b);
-          nc = (int)(fmaxf(hi_a - lo_a, hi_b - lo_b) + 1.0e-3f) + 1;
+          // longest window of the wavefront is at one of its ends, which are
+          // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126)
+          const float len = hi - lo;
+          const float len_a = __builtin_bit_cast(
+              float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0));
+          const float len_b = __builtin_bit_cast(
+              float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63));
+          nc = (int)(fmaxf(len_a, len_b) + 1.0e-3f) + 1;
           if (!zin) iv_lo = n_v;  // reads the column's empty entries only
         }
         switch (nc) {
