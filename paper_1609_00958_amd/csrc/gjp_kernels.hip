@@ -10,7 +10,11 @@
 // from zero-padded pair copies (one voxel of border on every side; each
 // element also holds its neighbour along one transverse axis), so the four
 // in-plane neighbours of a sample arrive in one wide load and the sampling
-// loop has no bounds tests.
+// loop has no bounds tests. The address path of the vector memory unit, not
+// bytes, bounds this loop (one tag lookup per quad of lanes per clock for
+// each load instruction, whatever its width), so for 16-bit storage a lane
+// may take two pixels of one detector column and serve both with one load of
+// three consecutive pair elements.
 //
 // Adjoint: exact transpose of the forward. A table pass stores, per ray of a
 // chunk of views, the setup the forward computes (driving axis, sample range,

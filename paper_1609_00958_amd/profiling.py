@@ -20,6 +20,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/gjp_kernels.hip", "csrc/gjp_ray.h")
@@ -51,11 +52,23 @@ def short_name(name: str):
     return None
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines, so that editing a comment
+    does not mark measured byte counts as stale."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = []
+    for line in text.splitlines():
+        line = re.sub(r"//.*$", "", line).rstrip()
+        if line.strip():
+            out.append(line)
+    return "\n".join(out)
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
@@ -225,7 +238,7 @@ def main():
     if a.counters:
         lines += ["", "Counters (last " + str(max(a.last, 1)) + " dispatches of each kernel):", ""]
         lines += counter_table(counters_last(a.counters, max(a.last, 1)))
-    lines += ["", f"Kernel source sha256: `{source_hash()}`", ""]
+    lines += ["", f"Kernel source sha256 (code without comments): `{source_hash()}`", ""]
     with open(a.out_md, "w") as f:
         f.write("\n".join(lines))
     if a.out_json:

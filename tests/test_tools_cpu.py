@@ -128,3 +128,12 @@ def test_profile_counter_table(tmp_path):
     # TA busy per CU: 8 * 8e5 / 8000 / 256 = 3.125 (a synthetic ratio)
     assert rows["address unit busy (TA)"] == "3.12"
     assert rows["L2 hit rate"] == "-"
+
+
+def test_source_hash_ignores_comments():
+    from paper_1609_00958_amd import profiling
+    a = "int f(int x) {  // first\n  return x + 1; /* two\n lines */\n}\n"
+    b = "// header\nint f(int x) {\n\n  return x + 1;\n}\n"
+    c = "int f(int x) {\n  return x + 2;\n}\n"
+    assert profiling._code_only(a) == profiling._code_only(b)
+    assert profiling._code_only(a) != profiling._code_only(c)
