@@ -119,8 +119,9 @@ gjp_status gjp_forward_project_naive(const gjp_geometry *g, const void *d_vol,
    the forward computes them. When every view's dv is parallel to axis 2 and no
    ray is driven by axis 2 (circular trajectories), each voxel gathers its
    contributions in registers; otherwise voxel tiles accumulate in LDS with
-   waves owning disjoint planes. No global atomics; each voxel is written by
-   one thread per launch, and the summation order is fixed. d_sino: device,
+   waves owning disjoint planes. No atomics touch the volume (the only global
+   atomic is an integer OR marking which driving axes each view uses); each
+   voxel is written by one thread per launch. d_sino: device,
    n_views*n_u*n_v floats. d_vol: device, n0*n1*n2 floats, overwritten.
    Per-ray tables for a chunk of views are taken from the stream-ordered pool
    during the call. Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */

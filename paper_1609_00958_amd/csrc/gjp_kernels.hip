@@ -22,8 +22,9 @@
 // For circular trajectories a voxel-driven gather evaluates, for each voxel
 // block, the few rays of each nearby detector column that reach it; otherwise
 // a splat pass accumulates ray samples into a voxel tile held in LDS. Both
-// recompute the forward's weights, sum in a fixed order and write each voxel
-// once per launch; no global atomics.
+// recompute the forward's weights and write each voxel once per launch; no
+// atomics touch the volume in memory (the table pass ORs a per-view mask of
+// driving axes).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -875,7 +876,7 @@ __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict
 // instruction cover PW consecutive planes of 64/PW rays taken far apart in the
 // batch, so they address distinct words. Odd plane strides in the padded LDS
 // layout spread consecutive planes over the banks. Each voxel is written to
-// memory once per chunk (no global atomics).
+// memory once per chunk (no atomics on the volume in memory).
 // proj: per view 12 floats, rows (u, v, w) of the map from a grid point q to
 // homogeneous detector coordinates, u = (A_u . q + b_u) / (A_w . q + b_w).
 // ---------------------------------------------------------------------------
