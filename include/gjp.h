@@ -166,7 +166,8 @@ gjp_status gjp_count_samples(const gjp_geometry *g, uint64_t *out);
    identical sinograms. The choice is kept in a process-wide cache keyed
    by the geometry's shape signature and dtype and used by later forward and
    batched calls. *tile_v_out receives the chosen number of detector pixels
-   along v per wavefront row (64, 32 or 16). Synchronises `stream`.
+   along v per wavefront row (64, 32 or 16; 128 for 16-bit storage when two
+   pixels per lane share their loads). Synchronises `stream`.
    Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
 gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
                                 float *d_sino, void *stream, int32_t *tile_v_out);
@@ -174,7 +175,9 @@ gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_
 /* Fix the launch configuration that forward calls (and, for the tile shape
    and view group, batched calls) use for geometries of this shape signature
    and dtype, as gjp_autotune_forward would: tile_v = detector pixels along v
-   per wavefront row (64, 32 or 16); view_group = consecutive views that take
+   per wavefront row (64, 32 or 16, or 128 for 16-bit storage: two pixels of
+   a detector column per lane, sharing their loads where the geometry allows;
+   batched calls take 64 for it); view_group = consecutive views that take
    their turn on each ray tile together (1 to 64); load_group = planes whose
    volume loads a lane issues together (2 or 4). Every configuration gives
    bitwise identical sinograms. Host-only. Errors: GJP_EINVAL. */
