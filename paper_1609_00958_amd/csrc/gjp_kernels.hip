@@ -1230,6 +1230,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
         const float4* R = RY + (size_t)iu * pitch;
         float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
         int nc = 0;  // wave-uniform bound on the candidates per lane
+        bool bounded = false;
+        float win_hi = 0.0f;
         int iv_lo = 0, iv_hi = n_v - 1;
         if (W0 > 1.0e-6f && W1 > 1.0e-6f) {
           // rays whose axis-2 coordinate lies in [z - 1, z + 2) on either plane
@@ -1245,19 +1247,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
             lo = fminf(fminf(a0, a1), fminf(c0, c1)) - margin;
             hi = fmaxf(fmaxf(a0, a1), fmaxf(c0, c1)) + margin;
           };
-          float lo, hi;
-          window(fz, lo, hi);
+          float lo;
+          window(fz, lo, win_hi);
+          bounded = true;
           iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
-          iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
           // an interval of length L holds at most floor(L) + 1 integers; the
           // longest window of the wavefront is at one of its ends, which are
-          // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126)
-          const float len = hi - lo;
-          const float len_a = __builtin_bit_cast(
-              float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0));
-          const float len_b = __builtin_bit_cast(
-              float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63));
-          nc = (int)(fmaxf(len_a, len_b) + 1.0e-3f) + 1;
+          // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126). The
+          // lengths are positive floats, whose bit patterns order as they do.
+          const float len = win_hi - lo;
+          const int len_a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0);
+          const int len_b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63);
+          nc = (int)(__builtin_bit_cast(float, max(len_a, len_b)) + 1.0e-3f) + 1;
           if (!zin) iv_lo = n_v;  // reads the column's empty entries only
         }
         switch (nc) {
@@ -1271,6 +1272,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           case 8: block_candidates<WF, 8>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
           default:
             // long or unbounded candidate ranges: explicit per-lane loop
+            if (bounded) iv_hi = min(n_v - 1, (int)floorf(fminf(win_hi, (float)n_v)));
             if (!zin) iv_hi = iv_lo - 1;
             for (int iv = iv_lo; iv <= iv_hi; ++iv) {
               const float4 r = R[iv];
