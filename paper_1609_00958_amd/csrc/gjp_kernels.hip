@@ -1209,15 +1209,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
       for (int iu = iu_lo; iu <= iu_hi; ++iu) {
         const float4 col = C[iu];
         if ((int)__float_as_uint(col.x) != m) continue;
-        int ia0, ia1;
-        float wfa0, wca0, wfa1, wca1;
-        sample_axis<WF>(fp0, col.z, col.y, ha, ia0, wfa0, wca0);
-        sample_axis<WF>(fp1, col.z, col.y, ha, ia1, wfa1, wca1);
-        // in-plane weights wA<plane><row> (rows va, va + 1)
-        const float wA00 = (ia0 == va) ? wfa0 : ((ia0 + 1 == va) ? wca0 : 0.0f);
-        const float wA01 = (ia0 == va + 1) ? wfa0 : ((ia0 == va) ? wca0 : 0.0f);
-        const float wA10 = !two ? 0.0f : ((ia1 == va) ? wfa1 : ((ia1 + 1 == va) ? wca1 : 0.0f));
-        const float wA11 = !two ? 0.0f : ((ia1 == va + 1) ? wfa1 : ((ia1 == va) ? wca1 : 0.0f));
+        // in-plane weights wA<plane><row> (rows va, va + 1; va is even, as z
+        // is, so the tents reproduce the forward's weights exactly)
+        float wA00, wA01, wA10, wA11;
+        pair_weights<WF>(fp0, col.z, col.y, ha, fva, va, wA00, wA01);
+        pair_weights<WF>(fp1, col.z, col.y, ha, fva, va, wA10, wA11);
+        if (!two) {
+          wA10 = 0.0f;
+          wA11 = 0.0f;
+        }
         if (wA00 == 0.0f && wA01 == 0.0f && wA10 == 0.0f && wA11 == 0.0f) continue;
         // v of the column's rays on each plane: (A + P6 z) / W, affine in z
         const float pa0 = __builtin_fmaf(fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
@@ -1230,8 +1230,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
         const float4* R = RY + (size_t)iu * pitch;
         float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
         int nc = 0;  // wave-uniform bound on the candidates per lane
-        bool bounded = false;
-        float win_hi = 0.0f;
+        float win_hi = 3.0e38f;  // upper end of the lane's window (none: every ray)
         int iv_lo = 0, iv_hi = n_v - 1;
         if (W0 > 1.0e-6f && W1 > 1.0e-6f) {
           // rays whose axis-2 coordinate lies in [z - 1, z + 2) on either plane
@@ -1249,7 +1248,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           };
           float lo;
           window(fz, lo, win_hi);
-          bounded = true;
           iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
           // an interval of length L holds at most floor(L) + 1 integers; the
           // longest window of the wavefront is at one of its ends, which are
@@ -1272,7 +1270,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           case 8: block_candidates<WF, 8>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
           default:
             // long or unbounded candidate ranges: explicit per-lane loop
-            if (bounded) iv_hi = min(n_v - 1, (int)floorf(fminf(win_hi, (float)n_v)));
+            iv_hi = min(n_v - 1, (int)floorf(fminf(win_hi, (float)n_v)));
             if (!zin) iv_hi = iv_lo - 1;
             for (int iv = iv_lo; iv <= iv_hi; ++iv) {
               const float4 r = R[iv];

@@ -443,3 +443,26 @@ def test_two_rays_per_lane_bitwise(gjp, oracle_mod, case):
     rounded = _to_dev(vol, dev).to(torch.float16).float().cpu().numpy()
     y = gjp.forward(_to_dev(vol, dev).to(torch.float16), G).cpu().numpy()
     assert rel_l2(y, oracle_mod.forward(og, rounded)) <= TOL32
+
+
+@pytest.mark.parametrize("beam", ["cone", "parallel"])
+def test_circular_spline_adjoint(gjp, oracle_mod, beam):
+    """Spline weights (Eq. 14) on circular trajectories: the column-form gather
+    with the forward's floor-and-select weights, against the oracle."""
+    dev = cuda()
+    shape = (38, 42, 60)
+    n_views, n_u, n_v = 11, 64, 90
+    if beam == "cone":
+        G = gjp.Geometry.circular_cone(shape, n_views, n_u, n_v, 170.0, 290.0, 1.1, 1.1,
+                                       weight="spline")
+    else:
+        G = gjp.Geometry.parallel(shape, n_views, n_u, n_v, 0.9, 0.8, weight="spline")
+    og = _oracle_geom(oracle_mod, G)
+    vol = workloads.rasterize(workloads.random_ellipsoids(131, shape), shape)
+    note(f"circular spline {beam}: forward")
+    y = gjp.forward(_to_dev(vol, dev), G).cpu().numpy()
+    assert rel_l2(y, oracle_mod.forward(og, vol)) <= TOL32
+    s = np.random.default_rng(132).uniform(0, 1, size=G.sino_shape).astype(np.float32)
+    note(f"circular spline {beam}: adjoint")
+    got = gjp.back(_to_dev(s, dev), G).cpu().numpy()
+    assert rel_l2(got, oracle_mod.adjoint(og, s)) <= TOL32
