@@ -1206,6 +1206,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
         iu_lo = 0;
         iu_hi = n_u - 1;
       }
+      // the projective rows' terms in the driving coordinate (fixed per plane)
+      // and their coefficients of the in-plane coordinate (the window below
+      // is a bound with margins, so this order of rounding is free)
+      const float PfA = (m == 0) ? P[4] : P[5], PaA = (m == 0) ? P[5] : P[4];
+      const float PfW = (m == 0) ? P[8] : P[9], PaW = (m == 0) ? P[9] : P[8];
+      const float KA0 = __builtin_fmaf(PfA, fp0, P[7]), KA1 = __builtin_fmaf(PfA, fp1, P[7]);
+      const float KW0 = __builtin_fmaf(PfW, fp0, P[11]), KW1 = __builtin_fmaf(PfW, fp1, P[11]);
       for (int iu = iu_lo; iu <= iu_hi; ++iu) {
         const float4 col = C[iu];
         if ((int)__float_as_uint(col.x) != m) continue;
@@ -1219,14 +1226,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           wA11 = 0.0f;
         }
         if (wA00 == 0.0f && wA01 == 0.0f && wA10 == 0.0f && wA11 == 0.0f) continue;
-        // v of the column's rays on each plane: (A + P6 z) / W, affine in z
+        // v of the column's rays on each plane: (A + P6 z) / W, affine in z;
+        // A and W are the plane terms (per axis) plus the column's in-plane term
         const float pa0 = __builtin_fmaf(fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
-        const float qx0 = (m == 0) ? fp0 : pa0, qy0 = (m == 0) ? pa0 : fp0;
-        const float qx1 = (m == 0) ? fp1 : pa1, qy1 = (m == 0) ? pa1 : fp1;
-        const float A0 = __builtin_fmaf(P[4], qx0, __builtin_fmaf(P[5], qy0, P[7]));
-        const float W0 = __builtin_fmaf(P[8], qx0, __builtin_fmaf(P[9], qy0, P[11]));
-        const float A1 = __builtin_fmaf(P[4], qx1, __builtin_fmaf(P[5], qy1, P[7]));
-        const float W1 = __builtin_fmaf(P[8], qx1, __builtin_fmaf(P[9], qy1, P[11]));
+        const float A0 = __builtin_fmaf(PaA, pa0, KA0), W0 = __builtin_fmaf(PaW, pa0, KW0);
+        const float A1 = __builtin_fmaf(PaA, pa1, KA1), W1 = __builtin_fmaf(PaW, pa1, KW1);
         const float4* R = RY + (size_t)iu * pitch;
         float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
         int nc = 0;  // wave-uniform bound on the candidates per lane
