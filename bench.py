@@ -157,7 +157,7 @@ def bench_batched(args, torch, gjp, workloads, dev):
     alg = 16.0 * S + 4.0 * n_rays
     achieved = alg / (avg * 1e-3) / 1e9
     out = {
-        "metric": "GJP ray-samples/s and % HBM roofline (fwd, adjoint, bf16) vs plain FP32 fwd",
+        "metric": "GJP ray-samples/s, batched FP32 forward of uneven instances",
         "value": S / (elapsed / args.steps),
         "unit": "ray-samples/s",
         "n_gpus": 1,
