@@ -1255,8 +1255,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
           // an interval of length L holds at most floor(L) + 1 integers; the
           // longest window of the wavefront is at one of its ends, which are
-          // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126). The
-          // lengths are positive floats, whose bit patterns order as they do.
+          // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126; every
+          // branch of the column loop is wave-uniform, so all 64 lanes are
+          // active here). The lengths are positive floats, whose bit patterns
+          // order as they do.
           const float len = win_hi - lo;
           const int len_a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0);
           const int len_b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63);
