@@ -180,95 +180,136 @@ static void ray_setup(const gjo_geom *g, int view, int iu, int iv, gjo_ray *ray)
   ray->len = sqrt(q);
 }
 
-/* Eq. 13 / Eq. 14 */
+/* Eq. 13 / Eq. 14: the weight of the lower neighbour at fractional offset
+   d in [0, 1]. */
 static double weight_fn(int kind, double d) {
   if (kind == GJO_W_SPLINE) return 1.0 - 3.0 * d * d + 2.0 * d * d * d;
   return 1.0 - d;
 }
 
-/* Volume element with zero padding outside the grid. dt: 0 = f64, 1 = f32. */
-static double vol_at(const gjo_geom *g, const void *vol, int dt, long long i0, long long i1,
-                     long long i2) {
-  if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= g->n[0] || i1 >= g->n[1] || i2 >= g->n[2])
-    return 0.0;
-  size_t idx = ((size_t)i0 * (size_t)g->n[1] + (size_t)i1) * (size_t)g->n[2] + (size_t)i2;
+/* Interpolation kernel of one transverse axis. Eqs. 10-12 give the two
+   neighbours of a coordinate p the weights w(p - floor p) and
+   1 - w(p - floor p); by the symmetry of Eq. 9 the second equals
+   w(ceil p - p). Both are therefore h(p - j) for the voxel index j, with
+   h(t) = w(|t|) for |t| < 1 and 0 elsewhere. At an integral p (Eq. 8) the
+   voxel j = p receives h(0) = w(0) = 1 and j = p + 1 receives h(-1) = 0. */
+static double kernel_1d(int kind, double t) {
+  const double a = fabs(t);
+  if (!(a < 1.0)) return 0.0;
+  return weight_fn(kind, a);
+}
+
+/* Voxel (j0, j1, j2) of a volume of the geometry, with the zero padding of
+   the in-volume reading: indices outside the grid read 0. dt: 0 = f64,
+   1 = f32. */
+static double voxel(const gjo_geom *g, const void *vol, int dt, const long long *j) {
+  for (int k = 0; k < 3; ++k)
+    if (j[k] < 0 || j[k] >= g->n[k]) return 0.0;
+  const size_t idx = ((size_t)j[0] * (size_t)g->n[1] + (size_t)j[1]) * (size_t)g->n[2] + (size_t)j[2];
   if (dt == 1) return (double)((const float *)vol)[idx];
   return ((const double *)vol)[idx];
 }
 
-static void vol_add(const gjo_geom *g, double *vol, long long i0, long long i1, long long i2,
-                    double v) {
-  if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= g->n[0] || i1 >= g->n[1] || i2 >= g->n[2]) return;
-  size_t idx = ((size_t)i0 * (size_t)g->n[1] + (size_t)i1) * (size_t)g->n[2] + (size_t)i2;
-  vol[idx] += v;
-}
-
-/* The sample at plane i (Eq. 6 with o = -s_m, as in Algorithm 1):
-   p = s + (o + i) r~, p_m := i. Returns 1 if p is inside the padded domain
-   and fills the floor/ceil corners and their weights (Eqs. 7-12). */
-typedef struct {
-  long long fl[3], cl[3];
-  double wfl[3], wcl[3];
-} gjo_sample;
-
-static int sample_at(const gjo_geom *g, const gjo_ray *ray, int i, gjo_sample *sm) {
+/* The point where the ray crosses plane i of its driving axis m (Eq. 6 with
+   the offset o = -s_m of Eq. 5): q = s + (i - s_m) r~, with q_m taken as the
+   integer i itself (Eq. 8). Returns 1 if the point is a sample of the ray:
+   both transverse coordinates inside the zero-padded domain (-1, N_k) and,
+   with cylinder clipping, the axis-0/axis-1 position strictly inside the
+   cylinder. */
+static int plane_point(const gjo_geom *g, const gjo_ray *ray, int i, double *q) {
   const int m = ray->m;
-  const double o = -ray->s[m]; /* Eq. 5 */
-  double p[3];
-  for (int k = 0; k < 3; ++k) p[k] = ray->s[k] + (o + (double)i) * ray->rt[k];
-  p[m] = (double)i;
-  for (int k = 0; k < 3; ++k)
-    if (!(p[k] > -1.0 && p[k] < (double)g->n[k])) return 0;
+  for (int k = 0; k < 3; ++k) q[k] = ray->s[k] + (-ray->s[m] + (double)i) * ray->rt[k];
+  q[m] = (double)i;
+  for (int k = 0; k < 3; ++k) {
+    if (k == m) continue;
+    if (!(q[k] > -1.0 && q[k] < (double)g->n[k])) return 0;
+  }
   if (g->clip) {
-    const double dx = p[0] - g->cyl_c[0], dy = p[1] - g->cyl_c[1];
+    const double dx = q[0] - g->cyl_c[0], dy = q[1] - g->cyl_c[1];
     if (!(dx * dx + dy * dy < g->cyl_r2)) return 0;
   }
-  for (int k = 0; k < 3; ++k) {
-    double f = floor(p[k]);
-    double c = ceil(p[k]);
-    sm->fl[k] = (long long)f;
-    sm->cl[k] = (long long)c;
-    sm->wfl[k] = weight_fn(g->weight, p[k] - f); /* Eq. 10, 11 */
-    sm->wcl[k] = 1.0 - sm->wfl[k];
-  }
-  sm->wfl[m] = 1.0; /* Eq. 11, driving axis */
-  sm->wcl[m] = 1.0;
   return 1;
 }
 
+/* The two transverse axes of driving axis m, in increasing order. */
+static void transverse_axes(int m, int *a, int *b) {
+  *a = (m == 0) ? 1 : 0;
+  *b = (m == 2) ? 1 : 2;
+}
+
+/* Value of the volume interpolated at a sample point q on plane q_m: the sum
+   over the 2 x 2 voxels of the plane whose indices bracket q on the two
+   transverse axes (Eq. 7), each weighted by the product of the two axes'
+   kernels (Eq. 12). */
+static double plane_interp(const gjo_geom *g, const void *vol, int dt, int m, const double *q) {
+  int a, b;
+  transverse_axes(m, &a, &b);
+  const long long base_a = (long long)floor(q[a]), base_b = (long long)floor(q[b]);
+  double sum = 0.0;
+  for (long long ja = base_a; ja <= base_a + 1; ++ja) {
+    const double ha = kernel_1d(g->weight, q[a] - (double)ja);
+    for (long long jb = base_b; jb <= base_b + 1; ++jb) {
+      const double hb = kernel_1d(g->weight, q[b] - (double)jb);
+      long long j[3];
+      j[m] = (long long)q[m];
+      j[a] = ja;
+      j[b] = jb;
+      sum += (ha * hb) * voxel(g, vol, dt, j);
+    }
+  }
+  return sum;
+}
+
+/* One ray of the forward projection (Algorithm 1): the interpolated values
+   at the ray's samples on the planes 0 .. N_m - 1 of its driving axis,
+   summed and scaled by the length of one plane step. */
 static double ray_forward(const gjo_geom *g, const void *vol, int dt, int view, int iu, int iv,
                           long long *count) {
   gjo_ray ray;
   ray_setup(g, view, iu, iv, &ray);
+  if (count) *count = 0;
   if (!ray.ok) return 0.0;
-  double acc = 0.0;
-  long long cnt = 0;
+  double sum = 0.0;
+  long long n = 0;
   for (int i = 0; i < g->n[ray.m]; ++i) {
-    gjo_sample q;
-    if (!sample_at(g, &ray, i, &q)) continue;
-    ++cnt;
-    /* Eq. 7 neighbours with Eq. 12 weights */
-    acc += vol_at(g, vol, dt, q.fl[0], q.fl[1], q.fl[2]) * (q.wfl[0] * q.wfl[1] * q.wfl[2]);
-    acc += vol_at(g, vol, dt, q.fl[0], q.cl[1], q.cl[2]) * (q.wfl[0] * q.wcl[1] * q.wcl[2]);
-    acc += vol_at(g, vol, dt, q.cl[0], q.fl[1], q.cl[2]) * (q.wcl[0] * q.wfl[1] * q.wcl[2]);
-    acc += vol_at(g, vol, dt, q.cl[0], q.cl[1], q.fl[2]) * (q.wcl[0] * q.wcl[1] * q.wfl[2]);
+    double q[3];
+    if (!plane_point(g, &ray, i, q)) continue;
+    sum += plane_interp(g, vol, dt, ray.m, q);
+    ++n;
   }
-  if (count) *count = cnt;
-  return ray.len * acc;
+  if (count) *count = n;
+  return ray.len * sum;
 }
 
+/* The transpose of ray_forward for one ray: each sample's 2 x 2 in-plane
+   voxels receive y times the step length times their kernel weights. */
 static void ray_adjoint(const gjo_geom *g, double y, int view, int iu, int iv, double *vol) {
   gjo_ray ray;
   ray_setup(g, view, iu, iv, &ray);
   if (!ray.ok || y == 0.0) return;
-  const double a = ray.len * y;
+  const double scaled = ray.len * y;
   for (int i = 0; i < g->n[ray.m]; ++i) {
-    gjo_sample q;
-    if (!sample_at(g, &ray, i, &q)) continue;
-    vol_add(g, vol, q.fl[0], q.fl[1], q.fl[2], a * (q.wfl[0] * q.wfl[1] * q.wfl[2]));
-    vol_add(g, vol, q.fl[0], q.cl[1], q.cl[2], a * (q.wfl[0] * q.wcl[1] * q.wcl[2]));
-    vol_add(g, vol, q.cl[0], q.fl[1], q.cl[2], a * (q.wcl[0] * q.wfl[1] * q.wcl[2]));
-    vol_add(g, vol, q.cl[0], q.cl[1], q.fl[2], a * (q.wcl[0] * q.wcl[1] * q.wfl[2]));
+    double q[3];
+    if (!plane_point(g, &ray, i, q)) continue;
+    int a, b;
+    transverse_axes(ray.m, &a, &b);
+    const long long base_a = (long long)floor(q[a]), base_b = (long long)floor(q[b]);
+    for (long long ja = base_a; ja <= base_a + 1; ++ja) {
+      const double ha = kernel_1d(g->weight, q[a] - (double)ja);
+      for (long long jb = base_b; jb <= base_b + 1; ++jb) {
+        const double hb = kernel_1d(g->weight, q[b] - (double)jb);
+        long long j[3];
+        j[ray.m] = i;
+        j[a] = ja;
+        j[b] = jb;
+        int in = 1;
+        for (int k = 0; k < 3; ++k) in &= (j[k] >= 0 && j[k] < g->n[k]);
+        if (!in) continue;
+        const size_t idx =
+            ((size_t)j[0] * (size_t)g->n[1] + (size_t)j[1]) * (size_t)g->n[2] + (size_t)j[2];
+        vol[idx] += scaled * (ha * hb);
+      }
+    }
   }
 }
 
@@ -423,8 +464,8 @@ long long gjo_count_samples(const int *shape, const double *voxel_size, const do
     ray_setup(&g, view, rem / n_v, rem % n_v, &ray);
     if (!ray.ok) continue;
     for (int i = 0; i < g.n[ray.m]; ++i) {
-      gjo_sample q;
-      total += sample_at(&g, &ray, i, &q);
+      double q[3];
+      total += plane_point(&g, &ray, i, q);
     }
   }
   return total;
