@@ -130,11 +130,18 @@ gjp_status gjp_back_project(const gjp_geometry *g, const float *d_sino, float *d
 
 /* Batched forward projection of n independent instances (geometry, volume,
    dtype, sinogram) in one persistent launch: work items (instance, view, ray
-   tile) are ordered longest-first and pulled from a device queue; the launch
-   sequence is captured in a HIP graph on first use for a given list of
-   geometries and replayed afterwards. Each sinogram is bitwise equal to the
-   one gjp_forward_project produces for the same instance and tile shape.
-   Arrays g, d_vols, dtypes, d_sinos are host arrays of length n >= 1.
+   tile) are pulled from a device queue, longest first by the host
+   double-precision sample count of a few rays per tile (groups of views of
+   one tile stay together); the launch sequence is captured in a HIP graph on
+   first use for a given list of geometries and replayed afterwards. Each
+   sinogram is bitwise equal to the one gjp_forward_project produces for the
+   same instance and tile shape. Arrays g, d_vols, dtypes, d_sinos are host
+   arrays of length n >= 1; every d_sinos[i] holds n_views*n_u*n_v floats.
+   Calls with the same geometry list share one plan (its device descriptors,
+   padded copies and queue counters); a call on any stream waits on the device
+   for the previous call of that plan to finish, so calls on different streams
+   are safe and run one after the other. At most 8 plans are kept (least
+   recently used evicted; evicting waits for that plan's last call only).
    Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
 gjp_status gjp_forward_project_batched(int32_t n, const gjp_geometry *const *g,
                                        const void *const *d_vols, const int32_t *dtypes,

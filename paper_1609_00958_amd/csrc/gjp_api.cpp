@@ -825,21 +825,27 @@ struct BatchPlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   BatchInst* staging = nullptr;  // pinned
-  hipEvent_t staged = nullptr;
+  hipEvent_t staged = nullptr;   // the descriptor upload has read `staging`
   bool staged_pending = false;
+  // The last replay has finished with the plan's device buffers (descriptors,
+  // padded copies, queue counters). A replay on any stream first waits for
+  // the previous one on the device, so replays of one plan never overlap.
+  hipEvent_t done = nullptr;
+  bool done_pending = false;
+  uint64_t last_use = 0;  // for least-recently-used eviction
   std::mutex mu;
 
   ~BatchPlan() {
-    if (staged) {
-      if (staged_pending) (void)hipEventSynchronize(staged);
-      (void)hipEventDestroy(staged);
-    }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     int cur = -1;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(device);
-    (void)hipDeviceSynchronize();
+    // the plan's own work only: no device-wide synchronisation
+    if (done && done_pending) (void)hipEventSynchronize(done);
+    if (staged && staged_pending) (void)hipEventSynchronize(staged);
+    if (done) (void)hipEventDestroy(done);
+    if (staged) (void)hipEventDestroy(staged);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (d_insts) (void)hipFree(d_insts);
     if (d_items) (void)hipFree(d_items);
     if (d_counter) (void)hipFree(d_counter);
@@ -851,6 +857,8 @@ struct BatchPlan {
 
 std::mutex g_plan_mu;
 std::map<std::string, std::shared_ptr<BatchPlan>> g_plans;
+uint64_t g_plan_clock = 0;  // guarded by g_plan_mu
+constexpr size_t kMaxPlans = 8;
 
 std::string plan_key(int n, const gjp_geometry* const* g, const int32_t* dtypes, int dvc) {
   std::string k = std::to_string(dvc);
@@ -860,6 +868,56 @@ std::string plan_key(int n, const gjp_geometry* const* g, const int32_t* dtypes,
     k += ":" + std::to_string(t.tile_v_log2);
   }
   return k;
+}
+
+// One group of work items of the batched launch and its estimated cost.
+struct WorkGroup {
+  int inst, v0, tile;
+  double cost;    // estimated samples of the group
+  double bucket;  // log-scale cost class for the ordering
+};
+
+// Estimated samples of each work group: the exact sample counts (the kernels'
+// own double-precision ray setup) of five rays per tile and view -- its four
+// corner pixels and its centre -- scaled to the tile's 256 rays, plus a fixed
+// per-ray setup cost.
+void estimate_group_costs(const gjp_geometry* const* g, const std::vector<BatchInst>& insts,
+                          std::vector<WorkGroup>& groups) {
+  unsigned nt = std::thread::hardware_concurrency();
+  if (nt == 0) nt = 1;
+  if (nt > 64) nt = 64;
+  if (groups.size() < 4096) nt = 1;
+  auto work = [&](unsigned t) {
+    for (size_t k = t; k < groups.size(); k += nt) {
+      WorkGroup& w = groups[k];
+      const gjp_geometry* G = g[w.inst];
+      const FwdArgs& a = insts[w.inst].a;
+      const int kv = a.tile_v_log2;
+      const int tu = w.tile / a.tiles_v, tv = w.tile - tu * a.tiles_v;
+      const int u_lo = tu * (256 >> kv), v_lo = tv << kv;
+      const int u_hi = std::min(G->n_u, u_lo + (256 >> kv)) - 1;
+      const int v_hi = std::min(G->n_v, v_lo + (1 << kv)) - 1;
+      const int pu[5] = {u_lo, u_lo, u_hi, u_hi, (u_lo + u_hi) / 2};
+      const int pv[5] = {v_lo, v_hi, v_lo, v_hi, (v_lo + v_hi) / 2};
+      const int kg = std::min(std::max(1, a.view_group), G->n_views - w.v0);
+      double samples = 0.0;
+      for (int v = w.v0; v < w.v0 + kg; ++v)
+        for (int r = 0; r < 5; ++r) {
+          gjp::RaySetup R;
+          gjp::ray_setup(G->views_grid.data() + 12 * (size_t)v, G->gg, pu[r], pv[r], R);
+          samples += (double)(R.i1 - R.i0);
+        }
+      const double rays = (double)(u_hi - u_lo + 1) * (double)(v_hi - v_lo + 1);
+      w.cost = samples / 5.0 * rays + 32.0 * rays * kg;
+    }
+  };
+  if (nt == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
 }
 
 gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes, int dvc,
@@ -878,12 +936,6 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
     pad_bytes += (size_t)(2 * copy_bytes(g[i]->n, dtypes[i]));
   }
   GJP_HIP(hipMalloc(&P->padded_all, pad_bytes), "batched: padded volumes");
-  // work items: instances ordered by cost per item (longest first), then view, tile
-  struct InstCost {
-    int inst;
-    double cost;
-  };
-  std::vector<InstCost> order;
   long long total_items = 0;
   for (int i = 0; i < n; ++i) {
     const double* d_views = nullptr;
@@ -905,35 +957,46 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
     I.weight = g[i]->weight;
     I.padded_elems = padded_elems(g[i]->n);
     I.idx64 = needs_idx64(g[i]->n, dtypes[i]) ? 1 : 0;
-    const int tile_rays = 256;
-    const double per_item = (double)tile_rays * std::max(g[i]->n[0], std::max(g[i]->n[1], g[i]->n[2]));
-    order.push_back({i, per_item});
     total_items += (long long)I.n_views * I.a.tiles_per_view;
   }
   if (total_items > (1ll << 31) - 1) return fail(GJP_EUNSUPPORTED, "batched: too many work items");
-  std::stable_sort(order.begin(), order.end(),
-                   [](const InstCost& x, const InstCost& y) { return x.cost > y.cost; });
+  // Work groups: (instance, group of view_group consecutive views, ray tile);
+  // a group's items are that tile for each view of the group in turn (the
+  // single launch's order: rays of nearby views share volume lines in L2).
+  std::vector<WorkGroup> groups;
+  try {
+    for (int i = 0; i < n; ++i) {
+      const BatchInst& I = P->host[i];
+      const int K = std::max(1, I.a.view_group);
+      for (int v0 = 0; v0 < I.n_views; v0 += K)
+        for (int t = 0; t < I.a.tiles_per_view; ++t) groups.push_back({i, v0, t, 0.0});
+    }
+  } catch (...) {
+    return fail(GJP_ENOMEM, "batched: work groups");
+  }
+  estimate_group_costs(g, P->host, groups);
+  // Longest first within each instance class, by the host double-precision
+  // sample count of a few rays per tile and view. Costs within about 20% of
+  // each other share a bucket, where the natural order (instance, views,
+  // tile) is kept for cache locality.
+  for (auto& w : groups)
+    w.bucket = w.cost > 0.0 ? std::floor(std::log(w.cost) / std::log(1.2)) : -1.0e9;
+  std::stable_sort(groups.begin(), groups.end(),
+                   [](const WorkGroup& x, const WorkGroup& y) { return x.bucket > y.bucket; });
   std::vector<uint2> items;
   try {
     items.reserve((size_t)total_items);
   } catch (...) {
     return fail(GJP_ENOMEM, "batched: work list");
   }
-  // classes in a fixed order; within a class, instances longest first; within
-  // an instance, groups of view_group views, each tile for all views of the
-  // group in turn (the single-instance launch order, for L2 reuse)
   for (int c = 0; c < gjp::kBatchClasses; ++c) {
     const size_t begin = items.size();
-    for (const auto& oc : order) {
-      const BatchInst& I = P->host[oc.inst];
+    for (const auto& w : groups) {
+      const BatchInst& I = P->host[w.inst];
       if (gjp::batch_class(I.dtype, I.weight, I.idx64) != c) continue;
-      const int K = std::max(1, I.a.view_group);
-      for (int v0 = 0; v0 < I.n_views; v0 += K) {
-        const int kg = std::min(K, I.n_views - v0);
-        for (int t = 0; t < I.a.tiles_per_view; ++t)
-          for (int v = v0; v < v0 + kg; ++v)
-            items.push_back(make_uint2((uint32_t)oc.inst | ((uint32_t)v << 12), (uint32_t)t));
-      }
+      const int kg = std::min(std::max(1, I.a.view_group), I.n_views - w.v0);
+      for (int v = w.v0; v < w.v0 + kg; ++v)
+        items.push_back(make_uint2((uint32_t)w.inst | ((uint32_t)v << 12), (uint32_t)w.tile));
     }
     if (items.size() > begin) {
       P->cls.push_back(c);
@@ -953,6 +1016,7 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
           "batched: queues");
   GJP_HIP(hipHostMalloc(&P->staging, (size_t)n * sizeof(BatchInst), 0), "batched: staging");
   GJP_HIP(hipEventCreateWithFlags(&P->staged, hipEventDisableTiming), "batched: event");
+  GJP_HIP(hipEventCreateWithFlags(&P->done, hipEventDisableTiming), "batched: event");
   // capture pad + queue reset + persistent kernel once
   hipStream_t cap;
   GJP_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "batched: capture stream");
@@ -1013,17 +1077,32 @@ extern "C" gjp_status gjp_forward_project_batched(int32_t n, const gjp_geometry*
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(key);
-    if (it != g_plans.end()) P = it->second;
+    if (it != g_plans.end()) {
+      P = it->second;
+      P->last_use = ++g_plan_clock;
+    }
   }
   if (!P) {
     gjp_status st = build_plan(n, g, dtypes, dvc, P);
     if (st != GJP_OK) return st;
+    std::shared_ptr<BatchPlan> evicted;  // released after the lock
     std::lock_guard<std::mutex> lk(g_plan_mu);
-    if (g_plans.size() >= 8) g_plans.erase(g_plans.begin());
+    if (g_plans.size() >= kMaxPlans) {
+      auto lru = g_plans.begin();
+      for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
+        if (it->second->last_use < lru->second->last_use) lru = it;
+      evicted = lru->second;
+      g_plans.erase(lru);
+    }
+    P->last_use = ++g_plan_clock;
     g_plans[key] = P;
   }
   std::lock_guard<std::mutex> lk(P->mu);
+  // the host staging buffer is free once the previous upload has read it
   if (P->staged_pending) GJP_HIP(hipEventSynchronize(P->staged), "batched: staging wait");
+  // the device buffers are free once the previous replay (on whatever
+  // stream) has finished: wait for it on this stream, without a host sync
+  if (P->done_pending) GJP_HIP(hipStreamWaitEvent(s, P->done, 0), "batched: replay order");
   for (int i = 0; i < n; ++i) {
     P->staging[i] = P->host[i];
     P->staging[i].src = d_vols[i];
@@ -1037,5 +1116,7 @@ extern "C" gjp_status gjp_forward_project_batched(int32_t n, const gjp_geometry*
   gjp::TimedLaunch t = gjp::timing_begin("batched", s);
   GJP_HIP(hipGraphLaunch(P->exec, s), "batched: graph launch");
   gjp::timing_end("batched", t, s);
+  GJP_HIP(hipEventRecord(P->done, s), "batched: completion event");
+  P->done_pending = true;
   return GJP_OK;
 }

@@ -208,6 +208,10 @@ def forward_batched(vols: Sequence, geoms: Sequence[Geometry], outs: Optional[Se
                 for v, g in zip(vols, geoms)]
     dev = vols[0].device
     for v, g, o in zip(vols, geoms, outs):
+        # the batched kernel writes float32 sinograms
+        if o.dtype != torch.float32:
+            raise TypeError("sinogram must be float32")
+        _dtype_code(v)
         _check_tensor(v, g.shape, "volume")
         _check_tensor(o, g.sino_shape, "sinogram")
         if v.device != dev or o.device != dev:
@@ -225,9 +229,15 @@ def forward_batched(vols: Sequence, geoms: Sequence[Geometry], outs: Optional[Se
 def autotune(vol, geom: Geometry, out=None) -> int:
     """Time the forward tile candidates for this geometry and dtype; returns tile_v."""
     torch = _torch()
+    if out is not None and out.dtype != torch.float32:
+        raise TypeError("sinogram must be float32")
+    _dtype_code(vol)
     _check_tensor(vol, geom.shape, "volume")
     if out is None:
         out = torch.empty(geom.sino_shape, dtype=torch.float32, device=vol.device)
+    _check_tensor(out, geom.sino_shape, "sinogram")
+    if out.device != vol.device:
+        raise ValueError("volume and sinogram must be on one device")
     tv = ctypes.c_int32()
     with torch.cuda.device(vol.device):
         check(lib().gjp_autotune_forward(geom.handle, vol.data_ptr(), _dtype_code(vol),

@@ -186,3 +186,60 @@ def test_sample_count_with_cylinder_clipping_circular(gjp, oracle_mod):
                                          pitch_u=0.9, pitch_v=1.1, clip_cylinder=True)):
         G = gjp.Geometry.from_config(cfg)
         assert G.count_samples() == oracle_mod.count_samples(oracle_mod.geometry_for(cfg))
+
+
+def test_binding_rejects_non_float32_outputs(gjp):
+    """The batched kernel and the autotuner write float32 sinograms: an output
+    of another dtype (half the bytes) is refused before anything is launched."""
+    import torch
+    G = gjp.Geometry.circular_cone((8, 8, 8), 4, 6, 6, 40.0, 60.0)
+    vol = torch.zeros(G.shape)
+    bad = torch.zeros(G.sino_shape, dtype=torch.bfloat16)
+    with pytest.raises(TypeError):
+        gjp.forward_batched([vol], [G], [bad])
+    with pytest.raises(TypeError):
+        gjp.autotune(vol, G, bad)
+    with pytest.raises(TypeError):
+        gjp.forward_batched([vol.to(torch.float64)], [G])
+
+
+_ENOMEM_SCRIPT = r"""
+import ctypes, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_1609_00958_amd import _lib  # constants and the descriptor layout only
+L = ctypes.CDLL(_lib.LIB_PATH)
+L.gjp_last_error.restype = ctypes.c_char_p
+n_views = (1 << 20) - 1
+views = np.zeros((n_views, 12))
+views[:, 6] = 1.0
+views[:, 10] = 1.0
+d = _lib.GeometryDesc()
+for k in range(3):
+    d.vol_shape[k] = 8
+    d.voxel_size[k] = 1.0
+d.n_views, d.n_u, d.n_v = n_views, 1, 1
+d.views = views.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+# the geometry keeps about 250 MB of host copies of the views; leave 64 MB
+vm = int(open("/proc/self/status").read().split("VmSize:")[1].split()[0]) * 1024
+resource.setrlimit(resource.RLIMIT_AS, (vm + (64 << 20), vm + (64 << 20)))
+h = ctypes.c_void_p()
+st = L.gjp_create_geometry(ctypes.byref(d), ctypes.byref(h))
+print(st, L.gjp_last_error().decode(), h.value)
+"""
+
+
+def test_host_allocation_failure_reports_enomem(tmp_path):
+    """A host allocation that fails (address space capped in a child process)
+    comes back as GJP_ENOMEM with a message, and no handle."""
+    import subprocess
+    import sys
+    from paper_1609_00958_amd import _lib
+    script = tmp_path / "enomem.py"
+    script.write_text(_ENOMEM_SCRIPT)
+    r = subprocess.run([sys.executable, str(script), ROOT], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    status, rest = r.stdout.strip().split(" ", 1)
+    assert int(status) == _lib.GJP_ENOMEM, r.stdout
+    assert "allocation" in rest and rest.endswith("None"), r.stdout
