@@ -1,15 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the generalized Joseph projector hot path on one MI355X.
 
-One step = one pass of the whole projection path over the synthetic workload
-(default: 256^3 volume of 12 seeded random ellipsoids, 360 cone-beam views
-over 360 degrees, 384 x 384 detector, magnification 1.5):
-  1. differentiable FP32 forward  y = A x        (autograd forward)
-  2. hand-written adjoint         A^T w          (autograd backward)
-  3. BF16-storage forward
-  4. FP16-storage forward
-`value` is ray-samples per second over the whole step (each pass processes the
-workload's exact sample count S). Inputs are resident in HBM before timing.
+Default workload (c3): a 512^3 Shepp-Logan-type volume (builder-defined
+stand-in, 10 nested ellipsoids), 720 cone-beam views over 360 degrees, 768 x
+768 detector, magnification 1.5. One step = one FP32 forward projection
+y = A x of all views (Algorithm 1); `value` is ray-samples per second, S / step
+time, with S the exact sample count of one pass (host FP64 ray setup). Inputs
+are resident in HBM before timing; the forward launch configuration is
+autotuned before the untimed warm-up.
+
+The same run then times, each after its own warm-up, and reports under
+`kernels`: the FP32 adjoint A^T y (table and gather passes), BF16 and FP16
+storage forwards and their speed-up over FP32, the plain one-lane-per-ray FP32
+forward, one batched launch of the 32-instance uneven workload, the paper's
+speed geometry (Table I: ms per projection), a 1024^3 BF16/FP16 forward and a
+2048^3 FP32 forward. `roofline` refers to the FP32 forward kernel and its
+binding unit (the vector-memory address path); the HBM fraction from the
+committed byte counters and the paper's access rate are reported beside it.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -26,6 +34,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# The vector-memory address path takes a wavefront load instruction whose lanes
+# hit irregular 16-byte (or 8-/12-byte) locations at 4 lanes per clock per
+# compute unit: 256 CUs x 2.4 GHz x 4 lane addresses.
+N_CU, CLOCK_HZ, ADDR_LANES_PER_CLK = 256, 2.4e9, 4
+ADDR_PEAK = N_CU * CLOCK_HZ * ADDR_LANES_PER_CLK
+# The paper's GJP_lin FP32 forward, volume in global memory (Table I, Sec.
+# IV-C geometry): ms per projection.
+PAPER_T1_MS = {"GTX 1080": 2.70, "GTX 970": 5.69}
+METRIC = "GJP ray-samples/s and % HBM roofline (fwd, adjoint, bf16) vs plain FP32 fwd"
 
 
 def log(msg):
@@ -43,30 +60,20 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def measured_copy_gbs(torch, dev):
-    """Device-to-device copy rate of a 2 GiB buffer (bytes read + written per
-    second), a measured stream peak to set beside the nominal HBM figure."""
-    src = torch.empty(1 << 29, dtype=torch.float32, device=dev).fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / 5
-    gbs = 2.0 * src.numel() * 4 / (ms * 1e-3) / 1e9
-    del src, dst
-    torch.cuda.empty_cache()
-    return gbs
+def host_threads():
+    """Threads the oracle may use: the environment's OpenMP setting (the
+    host's CPU share for this GPU), else the affinity mask."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return min(int(env), aff), aff
+    return aff, aff
 
 
 def measured_traffic(workload: str, kernel: str):
-    """HBM bytes per launch (fetch + write) of `kernel` from the committed rocprofv3
-    summary of this workload, or None if there is none or the kernel sources
-    changed since the counters were taken."""
+    """HBM bytes per launch (fetch, write) of `kernel` from the committed
+    rocprofv3 summary of this workload, or None if there is none or the kernel
+    sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -79,179 +86,234 @@ def measured_traffic(workload: str, kernel: str):
     fb, wb = k.get("fetch_bytes_per_launch"), k.get("write_bytes_per_launch")
     if fb is None or wb is None:
         return None
-    return fb + wb
+    return fb, wb
 
 
-def cpu_baseline(cfg, vol_np, target_s: float):
-    """Time the FP64 oracle forward on a bounded random sample of the workload's rays."""
+class Timer:
+    """Kernel times from the HIP events the library records around each of its
+    launches on their stream, plus the wall clock around the calls."""
+
+    def __init__(self, torch, gjp):
+        self.torch, self.gjp = torch, gjp
+
+    def run(self, fn, reps, kernels):
+        torch, gjp = self.torch, self.gjp
+        torch.cuda.synchronize()
+        gjp.timing_reset()
+        gjp.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        gjp.timing_enable(False)
+        out = {"wall_ms": 1e3 * wall}
+        for k in kernels:
+            ms, n = gjp.timing_read(k)
+            out[k] = {"ms_per_launch": ms / max(n, 1), "launches_per_call": n / reps,
+                      "ms_per_call": ms / reps}
+        return out
+
+
+def cpu_baseline(cfg, G_gjp, vol_np, target_s: float):
+    """The FP64 oracle forward on the host: a bounded sample of the workload's
+    rays on the host's thread share (sized to about target_s seconds), and the
+    seeded 1e5-ray subset on all of those threads and on one thread."""
     import oracle
     import workloads
     og = oracle.geometry_for(cfg)
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(int(cores), 16))
-    oracle.set_num_threads(cores)
-    # grow a probe until it runs for about a second, then size the sample
-    n_probe = 4000
-    while True:
-        probe = workloads.sample_rays(11, n_probe, cfg.n_views, cfg.n_u, cfg.n_v)
-        t0 = time.perf_counter()
-        _, c = oracle.forward_rays(og, vol_np, probe, with_counts=True)
-        dt = time.perf_counter() - t0
-        if dt >= 1.0 or n_probe >= cfg.n_rays:
-            break
-        n_probe = min(cfg.n_rays, n_probe * 4)
-    rate = max(int(c.sum()), 1) / max(dt, 1e-6)
-    n_rays = int(min(cfg.n_rays, max(4000, target_s * rate / max(c.mean(), 1.0))))
+    threads, aff = host_threads()
+    oracle.set_num_threads(threads)
+    sub = workloads.sample_rays(51, 100000, cfg.n_views, cfg.n_u, cfg.n_v)
+    t0 = time.perf_counter()
+    _, c = oracle.forward_rays(og, vol_np, sub, with_counts=True)
+    dt_sub = time.perf_counter() - t0
+    rate_sub = int(c.sum()) / dt_sub
+    n_rays = int(min(cfg.n_rays, max(100000, target_s * rate_sub / max(c.mean(), 1.0))))
     rays = workloads.sample_rays(12, n_rays, cfg.n_views, cfg.n_u, cfg.n_v)
     t0 = time.perf_counter()
-    _, c = oracle.forward_rays(og, vol_np, rays, with_counts=True)
+    _, c2 = oracle.forward_rays(og, vol_np, rays, with_counts=True)
     dt = time.perf_counter() - t0
-    samples = int(c.sum())
-    # the same oracle on one thread, over a slice of the sample sized for a few seconds
-    n1 = int(min(n_rays, max(1000, 3.0 * samples / dt / cores / max(c.mean(), 1.0))))
+    samples = int(c2.sum())
     oracle.set_num_threads(1)
     t1 = time.perf_counter()
-    _, c1 = oracle.forward_rays(og, vol_np, rays[:n1], with_counts=True)
+    _, c1 = oracle.forward_rays(og, vol_np, sub, with_counts=True)
     dt1 = time.perf_counter() - t1
-    oracle.set_num_threads(cores)
+    oracle.set_num_threads(threads)
     return {
         "value": samples / dt,
         "unit": "ray-samples/s",
-        "cores": cores,
+        "cores": threads,
         "kind": "oracle",
         "value_1core": int(c1.sum()) / dt1,
-        "sample": f"FP64 oracle forward of {n_rays} uniformly sampled rays of the workload "
-                  f"({samples} ray-samples, {dt:.1f} s, {cpu_model()}); value_1core: the "
-                  f"first {n1} of those rays on one thread ({dt1:.1f} s)",
+        "subset_1e5_all_threads": rate_sub,
+        "sample": f"FP64 oracle forward of {n_rays} uniformly sampled rays of the {cfg.name} "
+                  f"workload ({samples} ray-samples, {dt:.1f} s) on {threads} threads "
+                  f"(OpenMP; affinity mask {aff} CPUs, {cpu_model()}); value_1core: the seeded "
+                  f"1e5-ray subset on one thread ({dt1:.1f} s); subset_1e5_all_threads: the "
+                  f"same subset on {threads} threads ({dt_sub:.2f} s)",
     }
 
 
-def bench_batched(args, torch, gjp, workloads, dev):
-    """Batched workload: 32 uneven instances in one persistent, graph-replayed
-    launch; a step is one batched FP32 forward of all instances."""
+# ---------------------------------------------------------------------------
+# the auxiliary kernel figures (each a failure of its own, not of the line)
+# ---------------------------------------------------------------------------
+def _aux(name, fn, out):
+    import torch
+    t0 = time.perf_counter()
+    try:
+        out[name] = fn()
+        log(f"{name}: {json.dumps(out[name])[:300]} ({time.perf_counter() - t0:.1f} s)")
+    except (RuntimeError, MemoryError, ValueError) as e:
+        out[name] = {"error": str(e)[:300]}
+        log(f"{name} failed: {e}")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def aux_adjoint(T, torch, gjp, G, x, S, fwd_ms):
+    y = gjp.forward(x, G)
+    out = torch.empty_like(x)
+    gjp.back(y, G, out)
+    r = T.run(lambda: gjp.back(y, G, out), 2, ("adjoint_table", "adjoint_gather"))
+    ms = r["adjoint_table"]["ms_per_call"] + r["adjoint_gather"]["ms_per_call"]
+    return {"ms": ms, "wall_ms": r["wall_ms"], "ray_samples_per_s": S / (ms * 1e-3),
+            "table_ms": r["adjoint_table"]["ms_per_call"],
+            "gather_ms": r["adjoint_gather"]["ms_per_call"],
+            "gather_launches": r["adjoint_gather"]["launches_per_call"],
+            "ratio_to_f32_forward": ms / fwd_ms}
+
+
+def aux_dtypes(T, torch, gjp, G, x, S, fwd_ms, autotune):
+    res = {}
+    y = torch.empty(G.sino_shape, device=x.device)
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        xv = x.to(dt)
+        tile = gjp.autotune(xv, G, y) if autotune else None
+        gjp.forward(xv, G, y)
+        r = T.run(lambda: gjp.forward(xv, G, y), 3, ("forward",))
+        ms = r["forward"]["ms_per_launch"]
+        res[name] = {"ms": ms, "ray_samples_per_s": S / (ms * 1e-3), "tile_v": tile,
+                     "access_rate_GBps": 8.0 * S / (ms * 1e-3) / 1e9,
+                     "speedup_vs_f32": fwd_ms / ms}
+        del xv
+    return res
+
+
+def aux_naive(T, torch, gjp, G, x, S, fwd_ms):
+    y = torch.empty(G.sino_shape, device=x.device)
+    gjp.forward_naive(x, G, y)
+    r = T.run(lambda: gjp.forward_naive(x, G, y), 2, ("forward_naive",))
+    ms = r["forward_naive"]["ms_per_launch"]
+    return {"ms": ms, "ray_samples_per_s": S / (ms * 1e-3), "tuned_f32_speedup": ms / fwd_ms}
+
+
+def aux_batched(T, torch, gjp, workloads, dev):
     from workloads.configs import batched_instances
     insts = batched_instances()
-    t0 = time.perf_counter()
-    geoms, vols, S = [], [], 0
-    for cfg in insts:
-        G = gjp.Geometry.from_config(cfg)
-        geoms.append(G)
-        vols.append(workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev))
-        S += G.count_samples()
-    log(f"{len(insts)} instances ready in {time.perf_counter() - t0:.1f} s; S = {S}")
+    geoms = [gjp.Geometry.from_config(cfg) for cfg in insts]
+    vols = [workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev) for cfg in insts]
+    S = sum(G.count_samples() for G in geoms)
     outs = [torch.empty(G.sino_shape, dtype=torch.float32, device=dev) for G in geoms]
-    for _ in range(max(args.warmup, 1)):
-        gjp.forward_batched(vols, geoms, outs)
-    torch.cuda.synchronize()
-    gjp.timing_reset()
-    gjp.timing_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        gjp.forward_batched(vols, geoms, outs)
+    gjp.forward_batched(vols, geoms, outs)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    gjp.timing_enable(False)
-    b_ms, b_n = gjp.timing_read("batched")
-    avg = b_ms / max(b_n, 1)
-    n_rays = sum(G.n_views * G.n_u * G.n_v for G in geoms)
-    alg = 16.0 * S + 4.0 * n_rays
-    achieved = alg / (avg * 1e-3) / 1e9
-    out = {
-        "metric": "GJP ray-samples/s, batched FP32 forward of uneven instances",
-        "value": S / (elapsed / args.steps),
-        "unit": "ray-samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "c4: 32 uneven instances (edges 96-320, 90-360 views, "
-                               "128^2-512^2 detectors, cone or parallel) in one batched "
-                               "persistent launch; step = one batched FP32 forward",
-                   "ray_samples_per_pass": S, "rays_per_pass": n_rays},
-        "roofline": {"kernel": "batched", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("c4", "batched")},
-    }
-    print(json.dumps(out), flush=True)
+    plan_s = time.perf_counter() - t0
+    gjp.forward_batched(vols, geoms, outs)
+    r = T.run(lambda: gjp.forward_batched(vols, geoms, outs), 3, ("batched",))
+    ms = r["batched"]["ms_per_launch"]
+    return {"workload": "c4: 32 uneven instances (edges 96-320, 90-360 views, 128^2-512^2 "
+                        "detectors, cone or parallel) in one persistent graph-replayed launch",
+            "ms": ms, "wall_ms": r["wall_ms"], "ray_samples": S,
+            "ray_samples_per_s": S / (ms * 1e-3), "first_call_with_plan_s": plan_s}
 
 
-# The paper's GJP_lin FP32 forward with the volume in global memory (Table I,
-# Sec. IV-C geometry): ms per projection on its two GPUs.
-PAPER_T1_MS = {"GTX 1080": 2.70, "GTX 970": 5.69}
-
-
-def bench_t1(args, torch, gjp, workloads, dev):
-    """The paper's projection-speed geometry: 512^3 box clipped to the inscribed
-    cylinder, 512^2 detector, 10 degree cone, 360 views; a step is one FP32
-    forward of all views (Table I reports the time per projection)."""
+def aux_t1(T, torch, gjp, workloads, dev, autotune):
     cfg = workloads.config("t1")
     x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
     G = gjp.Geometry.from_config(cfg)
     S = G.count_samples()
-    out_t = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
-    if not args.no_autotune:
-        log(f"autotune float32: tile_v = {gjp.autotune(x, G, out_t)}")
+    y = torch.empty(G.sino_shape, device=dev)
+    tile = gjp.autotune(x, G, y) if autotune else None
+    gjp.forward(x, G, y)
+    r = T.run(lambda: gjp.forward(x, G, y), 3, ("forward",))
+    ms = r["forward"]["ms_per_launch"]
+    return {"workload": "t1: the paper's speed geometry (512^3 box clipped to the inscribed "
+                        "cylinder, 512^2 detector, 10 degree cone, 360 views), FP32",
+            "ms_per_projection": ms / cfg.n_views,
+            "wall_ms_per_projection": r["wall_ms"] / cfg.n_views,
+            "paper_ms_per_projection": PAPER_T1_MS, "ray_samples_per_s": S / (ms * 1e-3),
+            "access_rate_GBps": 16.0 * S / (ms * 1e-3) / 1e9, "tile_v": tile}
+
+
+def aux_c5a(T, torch, gjp, workloads, dev, tiles16):
+    cfg = workloads.config("c5a")
+    G = gjp.Geometry.from_config(cfg)
+    S = G.count_samples()
+    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    y = torch.empty(G.sino_shape, device=dev)
+    res = {"workload": "c5a: 1024^3, 1440 cone-beam views, 1536^2 detector; 16-bit storage, "
+                       "launch configuration of the 512^3 autotuning", "ray_samples": S}
+    for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        xv = x.to(dt)
+        if tiles16.get(name):
+            gjp.set_forward_tile(G, dt, *tiles16[name])
+        gjp.forward(xv, G, y)
+        r = T.run(lambda: gjp.forward(xv, G, y), 1, ("forward",))
+        ms = r["forward"]["ms_per_launch"]
+        res[name] = {"ms": ms, "ray_samples_per_s": S / (ms * 1e-3)}
+        del xv
+    return res
+
+
+def aux_c5b(T, torch, gjp, workloads, dev):
+    cfg = workloads.config("c5b")
+    G = gjp.Geometry.from_config(cfg)
+    S = G.count_samples()
+    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    y = torch.empty(G.sino_shape, device=dev)
+    gjp.forward(x, G, y)
+    r = T.run(lambda: gjp.forward(x, G, y), 1, ("forward", "pad"))
+    ms = r["forward"]["ms_per_launch"]
+    return {"workload": "c5b: 2048^3 FP32 (34 GB), 64 cone-beam views, 3072^2 detector",
+            "ms": ms, "pad_ms": r["pad"]["ms_per_launch"], "ray_samples": S,
+            "ray_samples_per_s": S / (ms * 1e-3)}
+
+
+# ---------------------------------------------------------------------------
+# alternative workloads for profiling runs (one JSON line each)
+# ---------------------------------------------------------------------------
+def bench_batched(args, torch, gjp, workloads, dev):
+    """A step is one batched FP32 forward of the 32 uneven instances."""
+    T = Timer(torch, gjp)
+    res = aux_batched(T, torch, gjp, workloads, dev)
+    from workloads.configs import batched_instances
+    insts = batched_instances()
+    geoms = [gjp.Geometry.from_config(cfg) for cfg in insts]
+    vols = [workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev) for cfg in insts]
+    outs = [torch.empty(G.sino_shape, device=dev) for G in geoms]
     for _ in range(max(args.warmup, 1)):
-        gjp.forward(x, G, out_t)
-    torch.cuda.synchronize()
-    gjp.timing_reset()
-    gjp.timing_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        gjp.forward(x, G, out_t)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    gjp.timing_enable(False)
-    f_ms, f_n = gjp.timing_read("forward")
-    avg = f_ms / max(f_n, 1)
-    ms_proj = 1e3 * elapsed / args.steps / cfg.n_views
-    alg = 16.0 * S + 4.0 * cfg.n_rays
-    achieved = alg / (avg * 1e-3) / 1e9
-    out = {
-        "metric": "GJP_lin FP32 forward, ms per projection (Table I geometry)",
-        "value": ms_proj,
-        "unit": "ms/projection",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": ms_proj / PAPER_T1_MS["GTX 1080"],
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "t1: 512^3 box clipped to the inscribed cylinder, 512^2 "
-                               "detector, 10 degree cone, 360 views; step = one FP32 forward",
-                   "ray_samples_per_pass": S, "rays_per_pass": cfg.n_rays,
-                   "ray_samples_per_s": S / (elapsed / args.steps),
-                   "paper_ms_per_projection": PAPER_T1_MS},
-        "roofline": {"kernel": "forward_f32", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("t1", "forward_f32")},
-    }
-    print(json.dumps(out), flush=True)
+        gjp.forward_batched(vols, geoms, outs)
+    r = T.run(lambda: gjp.forward_batched(vols, geoms, outs), args.steps, ("batched",))
+    S = res["ray_samples"]
+    print(json.dumps({
+        "metric": "GJP ray-samples/s, batched FP32 forward of uneven instances",
+        "value": S / (r["wall_ms"] * 1e-3), "unit": "ray-samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["wall_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": {"workload": res["workload"], "ray_samples_per_pass": S},
+        "kernels": {"batched_ms_per_launch": r["batched"]["ms_per_launch"]}}), flush=True)
 
 
 def bench_sart(args, torch, gjp, workloads, dev):
     """SART (Sec. IV-B) on the 256^3 / 360-view workload: 20 ordered subsets of
-    18 views; a step is one iteration (every subset updated once: one forward
-    and one adjoint over all views plus the elementwise steps)."""
+    18 views; a step is one iteration (every subset updated once)."""
     cfg = workloads.config("c2")
     x_true = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
     G = gjp.Geometry.from_config(cfg)
     S = G.count_samples()
     b = gjp.forward(x_true, G)
-    n_subsets = 20
-    t0 = time.perf_counter()
-    solver = gjp.SART(G, n_subsets, lam=1.0)
-    torch.cuda.synchronize()
-    log(f"SART set-up (row and column sums of {n_subsets} subsets): "
-        f"{time.perf_counter() - t0:.2f} s")
+    solver = gjp.SART(G, 20, lam=1.0)
     x = solver.run(b, max(args.warmup, 1))
     torch.cuda.synchronize()
     r0 = float(torch.linalg.vector_norm(b - gjp.forward(x, G)))
@@ -260,143 +322,38 @@ def bench_sart(args, torch, gjp, workloads, dev):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     r1 = float(torch.linalg.vector_norm(b - gjp.forward(x, G)))
-    out = {
+    print(json.dumps({
         "metric": "SART iterations: ray-samples/s (forward + adjoint per iteration)",
-        "value": 2 * S / (elapsed / args.steps),
-        "unit": "ray-samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
+        "value": 2 * S / (elapsed / args.steps), "unit": "ray-samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "sart: 256^3 random-ellipsoid volume, 360 cone-beam views, "
-                               "384x384 detector; 20 ordered subsets of 18 views, lambda 1; "
-                               "step = one SART iteration",
-                   "ray_samples_per_pass": S,
-                   "residual_norm_before_after": [r0, r1]},
-    }
-    print(json.dumps(out), flush=True)
-
-
-def bench_dtypes_512(args, torch, gjp, workloads, dev):
-    """FP32, BF16 and FP16 storage at 512^3 / 720 views / 768^2: each dtype
-    autotuned first (untimed); a step is one forward of each."""
-    cfg = workloads.config("c3")
-    G = gjp.Geometry.from_config(cfg)
-    S = G.count_samples()
-    if args.volume == "uniform":
-        # the kernels' work does not depend on voxel values; one fill kernel
-        # instead of the phantom's many small ones (for counter collection)
-        x = torch.rand(cfg.shape, device=dev, generator=torch.Generator(device=dev).manual_seed(3))
-    else:
-        x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
-    vols = [x, x.to(torch.bfloat16), x.to(torch.float16)]
-    y = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
-    tiles = [None if args.no_autotune else gjp.autotune(v, G, y) for v in vols]
-    log(f"autotuned tile_v f32 / bf16 / f16: {tiles}")
-    for _ in range(args.warmup):
-        for v in vols:
-            gjp.forward(v, G, y)
-    torch.cuda.synchronize()
-    gjp.timing_reset()
-    gjp.timing_enable(True)
-    t0 = time.perf_counter()
-    per = [0.0, 0.0, 0.0]
-    for _ in range(args.steps):
-        for k, v in enumerate(vols):
-            gjp.forward(v, G, y)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    gjp.timing_enable(False)
-    # per-dtype kernel times: one more launch of each, timed alone
-    for k, v in enumerate(vols):
-        gjp.timing_reset()
-        gjp.timing_enable(True)
-        gjp.forward(v, G, y)
-        torch.cuda.synchronize()
-        gjp.timing_enable(False)
-        ms, n = gjp.timing_read("forward")
-        per[k] = ms / n
-    out = {
-        "metric": "GJP forward ray-samples/s by volume storage type (FP32, BF16, FP16)",
-        "value": 3 * S / (elapsed / args.steps),
-        "unit": "ray-samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32/bf16/f16 storage, f32 math",
-        "data": "synthetic",
-        "config": {"workload": f"dtypes512: 512^3 {'uniform random' if args.volume == 'uniform' else 'Shepp-Logan-type'} "
-                               "volume, 720 cone-beam views, 768x768 detector; step = FP32 + "
-                               "BF16 + FP16 forward",
-                   "ray_samples_per_pass": S, "tile_v": tiles,
-                   "forward_ms": {"f32": per[0], "bf16": per[1], "f16": per[2]},
-                   "speedup_bf16_vs_f32": per[0] / per[1],
-                   "speedup_f16_vs_f32": per[0] / per[2]},
-    }
-    print(json.dumps(out), flush=True)
-
-
-def forward_dtypes_512(args, torch, gjp, workloads, dev):
-    """FP32, BF16 and FP16 forwards at 512^3 / 720 views / 768^2 (each after
-    its own autotuning, untimed), two timed launches each: the storage-type
-    comparison at the size the 16-bit target refers to."""
-    cfg = workloads.config("c3")
-    G = gjp.Geometry.from_config(cfg)
-    S = G.count_samples()
-    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
-    out = {"workload": f"{cfg.name}: {cfg.shape[0]}^3, {cfg.n_views} views, "
-                       f"{cfg.n_u}x{cfg.n_v} detector", "ray_samples_per_pass": S}
-    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
-        xv = x.to(dt)
-        y = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
-        tile = gjp.autotune(xv, G, y) if not args.no_autotune else None
-        gjp.forward(xv, G, y)
-        torch.cuda.synchronize()
-        gjp.timing_reset()
-        gjp.timing_enable(True)
-        for _ in range(2):
-            gjp.forward(xv, G, y)
-        torch.cuda.synchronize()
-        gjp.timing_enable(False)
-        ms, n = gjp.timing_read("forward")
-        out[name] = {"ms": ms / n, "ray_samples_per_s": S / (ms / n * 1e-3), "tile_v": tile}
-        log(f"512^3 forward {name}: {ms / n:.2f} ms (tile_v {tile})")
-        del xv, y
-    out["speedup_bf16_vs_f32"] = out["f32"]["ms"] / out["bf16"]["ms"]
-    out["speedup_f16_vs_f32"] = out["f32"]["ms"] / out["f16"]["ms"]
-    del x
-    torch.cuda.empty_cache()
-    return out
+                               "384x384 detector; 20 ordered subsets of 18 views, lambda 1",
+                   "ray_samples_per_pass": S, "residual_norm_before_after": [r0, r1]}}),
+          flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3",
+                    help="c3 (default), c1, c2, t1, c5a, c5b: step = one FP32 forward; "
+                         "c4: one batched forward; sart: one SART iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the forward autotuning that precedes the warm-up (untimed)")
-    ap.add_argument("--volume", choices=("phantom", "uniform"), default="phantom",
-                    help="dtypes512 only: the Shepp-Logan-type phantom or a uniform random "
-                         "volume (same work; fewer set-up kernels under a profiler)")
-    ap.add_argument("--no-512", action="store_true",
-                    help="skip the FP32 / BF16 / FP16 forward comparison at 512^3 (untimed "
-                         "by the step clock; reported under kernels)")
+    ap.add_argument("--no-aux", action="store_true",
+                    help="time the steps only (no auxiliary kernel figures): profiled runs")
+    ap.add_argument("--only-aux", default="",
+                    help="comma list of auxiliary figures to run (adjoint, dtypes, naive, "
+                         "batched, t1, c5a, c5b); default all")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy before the steps (untimed), a "
-                         "reference kernel of known traffic for hardware byte counters")
+                         "reference dispatch of known traffic for hardware byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -413,41 +370,21 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "c4":
         return bench_batched(args, torch, gjp, workloads, dev)
-    if args.workload == "t1":
-        return bench_t1(args, torch, gjp, workloads, dev)
     if args.workload == "sart":
         return bench_sart(args, torch, gjp, workloads, dev)
-    if args.workload == "dtypes512":
-        return bench_dtypes_512(args, torch, gjp, workloads, dev)
     cfg = workloads.config(args.workload)
     log(f"workload {cfg.name}: {cfg.shape} grid, {cfg.n_views} views, {cfg.n_u}x{cfg.n_v}")
     t0 = time.perf_counter()
-    ells = cfg.phantom_ellipsoids()
-    if int(np.prod(cfg.shape)) <= 256 ** 3:
-        vol_np = workloads.rasterize(ells, cfg.shape)
-        x = torch.from_numpy(vol_np).to(dev)
-    else:
-        x = workloads.rasterize_torch(ells, cfg.shape, dev)
-        vol_np = None
+    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
     G = gjp.Geometry.from_config(cfg)
     S = G.count_samples()
+    n_rays = cfg.n_rays
     log(f"phantom + geometry ready in {time.perf_counter() - t0:.1f} s; S = {S} ray-samples")
-    x_bf16 = x.to(torch.bfloat16)
-    x_f16 = x.to(torch.float16)
-    xr = x.clone().requires_grad_(True)
-    w = torch.rand(G.sino_shape, generator=torch.Generator().manual_seed(3)).to(dev)
+    y = torch.empty(G.sino_shape, dtype=torch.float32, device=dev)
+    tile = None
     if not args.no_autotune:
-        for v in (x, x_bf16, x_f16):
-            log(f"autotune {v.dtype}: tile_v = {gjp.autotune(v, G)}")
-    torch.cuda.synchronize()
-
-    def step():
-        xr.grad = None
-        y = gjp.project(xr, G)          # FP32 forward (autograd)
-        y.backward(w)                   # adjoint (hand-written backward)
-        gjp.forward(x_bf16, G)          # BF16 storage
-        gjp.forward(x_f16, G)           # FP16 storage
-
+        tile = gjp.autotune(x, G, y)
+        log(f"autotune float32: tile_v = {tile}")
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -456,146 +393,97 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    gjp.timing_reset()
-    gjp.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    gjp.timing_enable(False)
-    kern = {k: gjp.timing_read(k) for k in ("pad", "forward", "adjoint_table", "adjoint_gather")}
-    ms_per_step = 1e3 * elapsed / args.steps
-    samples_per_step = 4 * S
-    value = samples_per_step / (elapsed / args.steps)
+        gjp.forward(x, G, y)
+    T = Timer(torch, gjp)
+    r = T.run(lambda: gjp.forward(x, G, y), args.steps, ("forward", "pad"))
+    step_ms = r["wall_ms"]
+    fwd_ms = r["forward"]["ms_per_launch"]
+    value = S / (step_ms * 1e-3)
+    log(f"FP32 forward: {step_ms:.2f} ms per step (kernel {fwd_ms:.2f} ms, pad "
+        f"{r['pad']['ms_per_launch']:.2f} ms); {value:.4g} ray-samples/s")
 
-    # per-kernel figures (forward launches: f32, bf16, f16 in that order each step)
-    fwd_ms, fwd_n = kern["forward"]
-    gat_ms, gat_n = kern["adjoint_gather"]
-    tab_ms, tab_n = kern["adjoint_table"]
-    # per-dtype forward times: time each dtype separately, outside the timed steps
-    per_dtype = {}
-    for name, v, bps in (("f32", x, 16), ("bf16", x_bf16, 8), ("f16", x_f16, 8)):
-        gjp.timing_reset()
-        gjp.timing_enable(True)
-        for _ in range(3):
-            gjp.forward(v, G)
-        torch.cuda.synchronize()
-        gjp.timing_enable(False)
-        ms, n = gjp.timing_read("forward")
-        avg = ms / max(n, 1)
-        per_dtype[name] = {
-            "ms": avg,
-            "ray_samples_per_s": S / (avg * 1e-3),
-            "alg_GBps": (bps * S + 4 * G.n_views * G.n_u * G.n_v) / (avg * 1e-3) / 1e9,
-        }
-    # the plain one-lane-per-ray kernel on the same volumes, for context
-    naive = {}
-    for name, v, bps in (("f32", x, 16), ("bf16", x_bf16, 8)):
-        gjp.forward_naive(v, G)
-        torch.cuda.synchronize()
-        gjp.timing_reset()
-        gjp.timing_enable(True)
-        for _ in range(2):
-            gjp.forward_naive(v, G)
-        torch.cuda.synchronize()
-        gjp.timing_enable(False)
-        ms, n = gjp.timing_read("forward_naive")
-        avg = ms / max(n, 1)
-        naive[name] = {
-            "ms": avg,
-            "ray_samples_per_s": S / (avg * 1e-3),
-            "alg_GBps": (bps * S + 4 * G.n_views * G.n_u * G.n_v) / (avg * 1e-3) / 1e9,
-        }
-    n_rays = G.n_views * G.n_u * G.n_v
-    n_vox = int(np.prod(cfg.shape))
-    gat_avg = gat_ms / max(gat_n, 1)
-    adj_launches_per_step = max(gat_n // args.steps, 1)
-    adj_ms_step = (gat_ms + tab_ms) / args.steps
-    # algorithmic bytes of one gather launch: 16 B per sample of its view chunk, 4 B per
-    # ray of the chunk read and 4 B per voxel written
-    gat_bytes = (16.0 * S + 4.0 * n_rays + 4.0 * n_vox * adj_launches_per_step) / \
-        adj_launches_per_step
-    kernels = {
-        "forward_f32": per_dtype["f32"],
-        "forward_bf16": per_dtype["bf16"],
-        "forward_f16": per_dtype["f16"],
-        "adjoint": {
-            "ms": adj_ms_step,
-            "ray_samples_per_s": S / (adj_ms_step * 1e-3),
-            "gather_ms_per_launch": gat_avg,
-            "table_ms_per_step": tab_ms / args.steps,
-            "launches_per_step": adj_launches_per_step,
-        },
-        "speedup_bf16_vs_f32": per_dtype["f32"]["ms"] / per_dtype["bf16"]["ms"],
-        "speedup_f16_vs_f32": per_dtype["f32"]["ms"] / per_dtype["f16"]["ms"],
-        "forward_naive_f32": naive["f32"],
-        "forward_naive_bf16": naive["bf16"],
-        "speedup_f32_vs_naive_f32": naive["f32"]["ms"] / per_dtype["f32"]["ms"],
-        "speedup_bf16_vs_naive_f32": naive["f32"]["ms"] / per_dtype["bf16"]["ms"],
-    }
-    if not args.no_512:
-        # an auxiliary comparison: a failure here is reported, not fatal to the line
-        try:
-            kernels["forward_dtypes_512"] = forward_dtypes_512(args, torch, gjp, workloads, dev)
-        except (RuntimeError, MemoryError) as e:
-            kernels["forward_dtypes_512"] = {"error": str(e)[:200]}
-            torch.cuda.empty_cache()
-    # dominant kernel of the step
-    fwd_step_ms = fwd_ms / args.steps
-    if gat_ms >= fwd_ms / 3.0:
-        dom = "adjoint_gather"
-        achieved = gat_bytes / (gat_avg * 1e-3) / 1e9
-    else:
-        dom = "forward_f32"
-        achieved = per_dtype["f32"]["alg_GBps"]
-    # a profiled run (--calibrate-copy) keeps its 1 GiB copy the largest copy
-    # dispatch, which the byte-counter scaling takes as its reference
-    copy_gbs = None if args.calibrate_copy else measured_copy_gbs(torch, dev)
+    # roofline of the FP32 forward kernel: one irregular 16-byte pair load per
+    # sample and lane is one lane address on the vector-memory address path
+    achieved = S / (fwd_ms * 1e-3)
+    traffic = measured_traffic(cfg.name, "forward_f32")
     roofline = {
-        "kernel": dom,
-        "bound": "hbm",
+        "kernel": "forward_f32",
+        "bound": "vmem_address",
         "achieved": achieved,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS,
-        "measured_copy_GBps": copy_gbs,
-        "frac_of_measured_copy": achieved / copy_gbs if copy_gbs else None,
-        "traffic": measured_traffic(args.workload, "adjoint_gather" if dom == "adjoint_gather"
-                                    else "forward_f32"),
+        "peak": ADDR_PEAK,
+        "unit": "lane addresses/s (one per ray-sample)",
+        "frac": achieved / ADDR_PEAK,
+        "traffic": (traffic[0] + traffic[1]) if traffic else None,
+        "hbm_GBps": ((traffic[0] + traffic[1]) / (fwd_ms * 1e-3) / 1e9) if traffic else None,
+        "hbm_frac": ((traffic[0] + traffic[1]) / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        if traffic else None,
+        "access_rate_GBps": (16.0 * S + 4.0 * n_rays) / (fwd_ms * 1e-3) / 1e9,
+        "hbm_peak_GBps": HBM_PEAK_GBS,
     }
+    kernels = {"forward_f32": {"ms": fwd_ms, "ray_samples_per_s": achieved, "tile_v": tile,
+                               "pad_ms": r["pad"]["ms_per_launch"]}}
+    want = set(a for a in args.only_aux.split(",") if a) or {
+        "adjoint", "dtypes", "naive", "batched", "t1", "c5a", "c5b"}
+    if args.no_aux:
+        want = set()
+    if "adjoint" in want:
+        _aux("adjoint", lambda: aux_adjoint(T, torch, gjp, G, x, S, fwd_ms), kernels)
+    if "dtypes" in want:
+        def dts():
+            d = aux_dtypes(T, torch, gjp, G, x, S, fwd_ms, not args.no_autotune)
+            kernels["forward_bf16"], kernels["forward_f16"] = d["bf16"], d["f16"]
+            return {"speedup_bf16_vs_f32": d["bf16"]["speedup_vs_f32"],
+                    "speedup_f16_vs_f32": d["f16"]["speedup_vs_f32"]}
+        _aux("storage_speedups", dts, kernels)
+    if "naive" in want:
+        _aux("forward_naive_f32", lambda: aux_naive(T, torch, gjp, G, x, S, fwd_ms), kernels)
+    vol_np = None
+    if not args.no_cpu_baseline:
+        vol_np = x.cpu().numpy()
+    del x, y
+    torch.cuda.empty_cache()
+    if "batched" in want:
+        _aux("batched_c4", lambda: aux_batched(T, torch, gjp, workloads, dev), kernels)
+    if "t1" in want:
+        _aux("t1_table1_geometry", lambda: aux_t1(T, torch, gjp, workloads, dev,
+                                                  not args.no_autotune), kernels)
+    if "c5a" in want:
+        tiles16 = {}
+        for name in ("bf16", "f16"):
+            tv = kernels.get(f"forward_{name}", {}).get("tile_v")
+            if tv:
+                tiles16[name] = (tv, 16 if tv == 128 else 8, 2 if tv == 128 else 4)
+        _aux("c5a_1024_16bit", lambda: aux_c5a(T, torch, gjp, workloads, dev, tiles16), kernels)
+    if "c5b" in want:
+        _aux("c5b_2048_f32", lambda: aux_c5b(T, torch, gjp, workloads, dev), kernels)
+
     out = {
-        "metric": "GJP ray-samples/s and % HBM roofline (fwd, adjoint, bf16) vs plain FP32 fwd",
+        "metric": METRIC,
         "value": value,
         "unit": "ray-samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": step_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{cfg.name}: {cfg.shape[0]}^3 random-ellipsoid volume, {cfg.n_views} "
-                        f"cone-beam views, {cfg.n_u}x{cfg.n_v} detector; step = FP32 forward + "
-                        f"adjoint + BF16 forward + FP16 forward",
+            "workload": f"{cfg.name}: {cfg.shape[0]}x{cfg.shape[1]}x{cfg.shape[2]} "
+                        f"{'Shepp-Logan-type stand-in' if cfg.phantom == 'sl' else 'random-ellipsoid'} "
+                        f"volume, {cfg.n_views} {cfg.beam}-beam views, {cfg.n_u}x{cfg.n_v} "
+                        f"detector; step = one FP32 forward projection of all views",
             "ray_samples_per_pass": S,
             "rays_per_pass": n_rays,
-            "forward_ms_per_step": fwd_step_ms,
         },
-        "kernels": kernels,
         "roofline": roofline,
+        "kernels": kernels,
     }
     if not args.no_cpu_baseline:
-        if vol_np is None:
-            vol_np = x.cpu().numpy()
         log("timing the CPU oracle on a bounded ray sample")
-        out["cpu_baseline"] = cpu_baseline(cfg, vol_np, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, G, vol_np, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

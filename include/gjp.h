@@ -169,10 +169,16 @@ gjp_status gjp_count_samples(const gjp_geometry *g, uint64_t *out);
 /* Select the launch configuration of gjp_forward_project for this geometry
    and dtype (ray-tile shape, views interleaved per tile, planes whose loads a
    lane issues together) by timing candidates on `stream` with the caller's
-   buffers (d_sino is overwritten); every configuration gives bitwise
-   identical sinograms. The choice is kept in a process-wide cache keyed
-   by the geometry's shape signature and dtype and used by later forward and
-   batched calls. *tile_v_out receives the chosen number of detector pixels
+   buffers (d_sino is overwritten); the sums do not depend on the
+   configuration beyond rounding order (every one matches the oracle within
+   the stated tolerance). The choice is kept for this process, keyed by the
+   geometry's shape signature (grid, views, detector, beam, weight) and dtype,
+   and used by later forward and batched calls. If the environment variable
+   GJP_TUNE_CACHE names a file, the choice is also written there (one line
+   per entry, tagged with the device's architecture name and compute-unit
+   count; replaced atomically by rename) and later processes on the same kind
+   of device read it instead of the default; an unreadable or unwritable
+   file is ignored. *tile_v_out receives the chosen number of detector pixels
    along v per wavefront row (64, 32 or 16; 128 for 16-bit storage when two
    pixels per lane share their loads). Synchronises `stream`.
    Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
@@ -180,16 +186,25 @@ gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_
                                 float *d_sino, void *stream, int32_t *tile_v_out);
 
 /* Fix the launch configuration that forward calls (and, for the tile shape
-   and view group, batched calls) use for geometries of this shape signature
-   and dtype, as gjp_autotune_forward would: tile_v = detector pixels along v
-   per wavefront row (64, 32 or 16, or 128 for 16-bit storage: two pixels of
-   a detector column per lane, sharing their loads where the geometry allows;
-   batched calls take 64 for it); view_group = consecutive views that take
-   their turn on each ray tile together (1 to 64); load_group = planes whose
-   volume loads a lane issues together (2 or 4). Every configuration gives
-   bitwise identical sinograms. Host-only. Errors: GJP_EINVAL. */
+   and view group, batched calls) use in this process for geometries of this
+   shape signature and dtype, as gjp_autotune_forward would: tile_v =
+   detector pixels along v per wavefront row (64, 32 or 16, or 128 for 16-bit
+   storage: two pixels of a detector column per lane, sharing their loads
+   where the geometry allows; batched calls take 64 for it); view_group =
+   consecutive views that take their turn on each ray tile together (1 to
+   64); load_group = planes whose volume loads a lane issues together (2 or
+   4). tile_v = 0 removes this process's choice (the on-disk cache or the
+   default applies again; the other arguments are ignored). Not written to
+   the on-disk cache. Host-only. Errors: GJP_EINVAL. */
 gjp_status gjp_set_forward_tile(const gjp_geometry *g, int32_t vol_dtype, int32_t tile_v,
                                 int32_t view_group, int32_t load_group);
+
+/* The launch configuration gjp_forward_project would use now for this
+   geometry's shape signature and dtype (this process's choice, else the
+   on-disk cache's entry for the current device, else the default 64 / 8 / 4).
+   Errors: GJP_EINVAL (null pointer, unknown dtype). */
+gjp_status gjp_get_forward_tile(const gjp_geometry *g, int32_t vol_dtype, int32_t *tile_v,
+                                int32_t *view_group, int32_t *load_group);
 
 /* SART (the reconstruction of Sec. IV-B, after Andersen and Kak): the two
    elementwise steps of one subset update

@@ -23,7 +23,8 @@ EXPORTS = (
     "gjp_create_geometry", "gjp_destroy_geometry", "gjp_forward_project",
     "gjp_forward_project_naive", "gjp_back_project",
     "gjp_forward_project_batched", "gjp_views_circular_cone", "gjp_views_parallel",
-    "gjp_count_samples", "gjp_autotune_forward", "gjp_set_forward_tile", "gjp_timing_enable",
+    "gjp_count_samples", "gjp_autotune_forward", "gjp_set_forward_tile", "gjp_get_forward_tile",
+    "gjp_timing_enable",
     "gjp_timing_reset",
     "gjp_timing_read", "gjp_last_error", "gjp_sart_residual", "gjp_sart_update",
 )
@@ -78,6 +79,8 @@ def lib():
     L.gjp_count_samples.argtypes = [vp, ctypes.POINTER(u64)]
     L.gjp_autotune_forward.argtypes = [vp, vp, i32, vp, vp, ctypes.POINTER(i32)]
     L.gjp_set_forward_tile.argtypes = [vp, i32, i32, i32, i32]
+    L.gjp_get_forward_tile.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]
     L.gjp_timing_enable.argtypes = [i32]
     L.gjp_timing_reset.argtypes = []
     L.gjp_timing_read.argtypes = [ctypes.c_char_p, f64p, ctypes.POINTER(i64)]

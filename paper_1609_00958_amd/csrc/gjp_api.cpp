@@ -16,6 +16,11 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <set>
+#include <sstream>
+#include <unistd.h>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -498,12 +503,19 @@ extern "C" gjp_status gjp_count_samples(const gjp_geometry* g, uint64_t* out) {
 // ---------------------------------------------------------------------------
 static std::once_flag g_pool_once[gjp_geometry::kMaxDev];
 
+// The stream-ordered pool keeps up to this many freed bytes for reuse (the
+// padded copies of repeated 512^3 forwards, the adjoint's ray tables); larger
+// scratch, such as the padded copies of a 2048^3 volume, goes back to the
+// device at the next synchronisation instead of staying cached beside the
+// caller's own allocator.
+static const uint64_t kPoolKeepBytes = (uint64_t)8 << 30;
+
 static void keep_pool_memory(int dvc) {
   if (dvc < 0 || dvc >= gjp_geometry::kMaxDev) return;
   std::call_once(g_pool_once[dvc], [dvc]() {
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dvc) == hipSuccess) {
-      uint64_t thr = UINT64_MAX;
+      uint64_t thr = kPoolKeepBytes;
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
   });
@@ -520,8 +532,13 @@ static hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s) {
 // forward
 // ---------------------------------------------------------------------------
 namespace {
+// Launch configurations of the forward by shape signature and dtype: set in
+// this process (autotuner, gjp_set_forward_tile), else read from the on-disk
+// cache named by GJP_TUNE_CACHE for the current device, else the default.
 std::mutex g_tune_mu;
-std::map<std::string, FwdTile> g_tune;
+std::map<std::string, FwdTile> g_tune;                 // this process
+std::map<std::string, FwdTile> g_disk;                 // device tag + key -> entry
+std::set<std::string> g_disk_loaded;                   // device tags read from disk
 
 std::string tune_key(const gjp_geometry* g, int dtype) {
   char buf[256];
@@ -530,10 +547,104 @@ std::string tune_key(const gjp_geometry* g, int dtype) {
   return buf;
 }
 
+const char* tune_cache_path() {
+  const char* p = getenv("GJP_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+// Architecture name and compute-unit count of the current device ("" if there
+// is none): cache entries measured on one kind of device are not used on
+// another.
+std::string device_tag() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return "";
+  static std::mutex mu;
+  static std::map<int, std::string> tags;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = tags.find(d);
+  if (it != tags.end()) return it->second;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, d) != hipSuccess) return "";
+  std::string tag = std::string(p.gcnArchName) + "/" + std::to_string(p.multiProcessorCount) + "cu";
+  for (char& c : tag)
+    if (c == ' ' || c == '\t') c = '_';
+  tags[d] = tag;
+  return tag;
+}
+
+// Cache file: one entry per line, "<device> <key> <tile_v_log2> <view_group>
+// <load_group>"; lines that do not parse are ignored.
+bool parse_entry(const std::string& line, std::string& dev, std::string& key, FwdTile& t) {
+  std::istringstream in(line);
+  int k = 0, vg = 0, rg = 0;
+  if (!(in >> dev >> key >> k >> vg >> rg)) return false;
+  if (k < 4 || k > 7 || vg < 1 || vg > 64 || (rg != 2 && rg != 4)) return false;
+  t = FwdTile();
+  t.tile_v_log2 = k;
+  t.view_group = vg;
+  t.ru_group = rg;
+  return true;
+}
+
+// Reads the cache's entries for `dev` once per device (caller holds g_tune_mu).
+void disk_load(const std::string& dev) {
+  if (dev.empty() || g_disk_loaded.count(dev)) return;
+  g_disk_loaded.insert(dev);
+  const char* path = tune_cache_path();
+  if (!path) return;
+  std::ifstream f(path);
+  std::string line, d, key;
+  FwdTile t;
+  while (std::getline(f, line))
+    if (parse_entry(line, d, key, t) && d == dev) g_disk[d + " " + key] = t;
+}
+
+// Adds or replaces one entry in the cache file (written to a temporary file
+// and renamed over the old one). Failures leave the file as it was; the
+// choice still applies in this process.
+void disk_store(const std::string& dev, const std::string& key, const FwdTile& t) {
+  const char* path = tune_cache_path();
+  if (!path || dev.empty()) return;
+  std::vector<std::string> lines;
+  {
+    std::ifstream f(path);
+    std::string line, d, k;
+    FwdTile o;
+    while (std::getline(f, line)) {
+      if (parse_entry(line, d, k, o) && d == dev && k == key) continue;
+      if (!line.empty()) lines.push_back(line);
+    }
+  }
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s %s %d %d %d", dev.c_str(), key.c_str(), t.tile_v_log2,
+           t.view_group, t.ru_group);
+  lines.push_back(buf);
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return;
+    for (const auto& l : lines) f << l << "\n";
+    if (!f.good()) {
+      f.close();
+      (void)remove(tmp.c_str());
+      return;
+    }
+  }
+  if (rename(tmp.c_str(), path) != 0) (void)remove(tmp.c_str());
+  g_disk[dev + " " + key] = t;
+}
+
 FwdTile tile_for(const gjp_geometry* g, int dtype) {
+  const std::string key = tune_key(g, dtype);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(tune_key(g, dtype));
+  auto it = g_tune.find(key);
   if (it != g_tune.end()) return it->second;
+  if (tune_cache_path()) {
+    const std::string dev = device_tag();
+    disk_load(dev);
+    auto jt = g_disk.find(dev + " " + key);
+    if (jt != g_disk.end()) return jt->second;
+  }
   return FwdTile();
 }
 
@@ -710,8 +821,12 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
   (void)hipEventDestroy(e1);
   if (st != GJP_OK) return st;
   {
+    const std::string key = tune_key(g, vol_dtype);
+    const std::string dev = tune_cache_path() ? device_tag() : std::string();
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(g, vol_dtype)] = best;
+    g_tune[key] = best;
+    disk_load(dev);
+    disk_store(dev, key, best);
   }
   if (tile_v_out) *tile_v_out = 1 << best.tile_v_log2;
   return GJP_OK;
@@ -723,6 +838,11 @@ extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dt
   if (!g) return fail(GJP_EINVAL, "gjp_set_forward_tile: geometry is null");
   if (vol_dtype != GJP_F32 && vol_dtype != GJP_BF16 && vol_dtype != GJP_F16)
     return fail(GJP_EINVAL, "gjp_set_forward_tile: unknown dtype");
+  if (tile_v == 0) {  // forget this process's choice
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.erase(tune_key(g, vol_dtype));
+    return GJP_OK;
+  }
   FwdTile t;
   if (tile_v == 128 && vol_dtype != GJP_F32) t.tile_v_log2 = 7;
   else if (tile_v == 64) t.tile_v_log2 = 6;
@@ -739,6 +859,20 @@ extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dt
   t.ru_group = load_group;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune[tune_key(g, vol_dtype)] = t;
+  return GJP_OK;
+}
+
+extern "C" gjp_status gjp_get_forward_tile(const gjp_geometry* g, int32_t vol_dtype,
+                                           int32_t* tile_v, int32_t* view_group,
+                                           int32_t* load_group) {
+  if (!g || !tile_v || !view_group || !load_group)
+    return fail(GJP_EINVAL, "gjp_get_forward_tile: null pointer");
+  if (vol_dtype != GJP_F32 && vol_dtype != GJP_BF16 && vol_dtype != GJP_F16)
+    return fail(GJP_EINVAL, "gjp_get_forward_tile: unknown dtype");
+  const FwdTile t = tile_for(g, vol_dtype);
+  *tile_v = 1 << t.tile_v_log2;
+  *view_group = t.view_group;
+  *load_group = t.ru_group;
   return GJP_OK;
 }
 

@@ -477,10 +477,7 @@ __device__ __forceinline__ void pair_quads(const Triple& t, bool up, const bf16_
 // One 12-byte load of the pair elements at floors z, z + 1, z + 2 of the first
 // ray then serves both. Each ray accumulates exactly the terms, in the same
 // order and with the same arithmetic, as the one-ray loop.
-#ifndef GJP_PAIR_GROUP
-#define GJP_PAIR_GROUP 2
-#endif
-constexpr int kPairGroup = GJP_PAIR_GROUP;  // planes per load group (two samples each)
+constexpr int kPairGroup = 2;  // planes per load group (two samples each)
 
 template <typename T, int WF, int GRP>
 __device__ __forceinline__ void fwd_loop_rowuniform_pair(const FwdArgs& a, const RaySetup& R1,
@@ -735,14 +732,9 @@ __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
   fwd_block<T, WF, IDX64, GRP, false>(a);
 }
 
-#ifdef GJP_PAIR_WPE
-#define GJP_PAIR_ATTR __attribute__((amdgpu_waves_per_eu(GJP_PAIR_WPE)))
-#else
-#define GJP_PAIR_ATTR
-#endif
 // Two rays per lane (16-bit storage, 128-wide tiles).
 template <typename T, int WF, bool IDX64, int GRP>
-__global__ __launch_bounds__(256) GJP_PAIR_ATTR void fwd_pair_kernel(const FwdArgs a) {
+__global__ __launch_bounds__(256) void fwd_pair_kernel(const FwdArgs a) {
   fwd_block<T, WF, IDX64, GRP, true>(a);
 }
 

@@ -257,6 +257,25 @@ def set_forward_tile(geom: Geometry, dtype, tile_v: int, view_group: int = 8,
                                      int(load_group)))
 
 
+def reset_forward_tile(geom: Geometry, dtype) -> None:
+    """Forget this process's launch configuration for the geometry's shape
+    signature and dtype (the on-disk cache or the default applies again)."""
+    torch = _torch()
+    code = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}[dtype]
+    check(lib().gjp_set_forward_tile(geom.handle, code, 0, 0, 0))
+
+
+def get_forward_tile(geom: Geometry, dtype):
+    """(tile_v, view_group, load_group) that forward calls use now for this
+    geometry's shape signature and dtype."""
+    torch = _torch()
+    code = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}[dtype]
+    tv, vg, lg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().gjp_get_forward_tile(geom.handle, code, ctypes.byref(tv), ctypes.byref(vg),
+                                     ctypes.byref(lg)))
+    return int(tv.value), int(vg.value), int(lg.value)
+
+
 def timing_enable(on: bool = True) -> None:
     check(lib().gjp_timing_enable(1 if on else 0))
 

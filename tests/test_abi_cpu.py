@@ -243,3 +243,27 @@ def test_host_allocation_failure_reports_enomem(tmp_path):
     status, rest = r.stdout.strip().split(" ", 1)
     assert int(status) == _lib.GJP_ENOMEM, r.stdout
     assert "allocation" in rest and rest.endswith("None"), r.stdout
+
+
+def test_forward_tile_query_and_reset(gjp):
+    """Host-only launch configuration: set, query, forget (default 64 / 8 / 4)."""
+    import torch
+    G = gjp.Geometry.circular_cone((12, 10, 14), 5, 9, 11, 60.0, 90.0)
+    assert gjp.get_forward_tile(G, torch.float32) == (64, 8, 4)
+    gjp.set_forward_tile(G, torch.float32, 32, 5, 2)
+    gjp.set_forward_tile(G, torch.bfloat16, 128, 16, 2)
+    assert gjp.get_forward_tile(G, torch.float32) == (32, 5, 2)
+    assert gjp.get_forward_tile(G, torch.bfloat16) == (128, 16, 2)
+    # the key is the shape signature: a second handle of the same shape shares it
+    G2 = gjp.Geometry.circular_cone((12, 10, 14), 5, 9, 11, 70.0, 95.0)
+    assert gjp.get_forward_tile(G2, torch.float32) == (32, 5, 2)
+    gjp.reset_forward_tile(G, torch.float32)
+    assert gjp.get_forward_tile(G, torch.float32) == (64, 8, 4)
+    assert gjp.get_forward_tile(G, torch.bfloat16) == (128, 16, 2)
+    from paper_1609_00958_amd import _lib
+    L = _lib.lib()
+    i = ctypes.c_int32()
+    assert L.gjp_get_forward_tile(None, 0, ctypes.byref(i), ctypes.byref(i),
+                                  ctypes.byref(i)) == _lib.GJP_EINVAL
+    assert L.gjp_get_forward_tile(G.handle, 5, ctypes.byref(i), ctypes.byref(i),
+                                  ctypes.byref(i)) == _lib.GJP_EINVAL

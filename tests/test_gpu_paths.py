@@ -435,3 +435,30 @@ def test_full_c3_differentiable(gjp, oracle_mod):
     note(f"c3 differentiable: 20 steps in {time.perf_counter() - t0:.2f} s, "
          f"loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert all(l2 < l1 for l1, l2 in zip(losses, losses[1:]))
+
+
+def test_autotune_cache_on_disk(gjp, tmp_path, monkeypatch):
+    """GJP_TUNE_CACHE: the autotuner's choice is written to the file, tagged
+    with the device, and read back once this process's own choice is
+    forgotten; a shape signature without an entry keeps the default."""
+    import torch
+    dev = cuda()
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("GJP_TUNE_CACHE", str(path))
+    shape = (36, 30, 44)
+    G = gjp.Geometry.circular_cone(shape, 9, 50, 70, 150.0, 225.0)
+    x = torch.rand(shape, generator=torch.Generator().manual_seed(9)).to(dev)
+    note("autotune with on-disk cache")
+    tv = gjp.autotune(x, G)
+    chosen = gjp.get_forward_tile(G, torch.float32)
+    assert chosen[0] == tv
+    lines = [l.split() for l in path.read_text().splitlines() if l.strip()]
+    assert len(lines) == 1 and lines[0][0].startswith("gfx")
+    assert [int(v) for v in lines[0][2:]] == [{64: 6, 32: 5, 16: 4}[tv], chosen[1], chosen[2]]
+    gjp.reset_forward_tile(G, torch.float32)
+    assert gjp.get_forward_tile(G, torch.float32) == chosen
+    # same sizes, another dtype: no entry
+    assert gjp.get_forward_tile(G, torch.float16) == (64, 8, 4)
+    ref = gjp.forward(x, G)
+    gjp.set_forward_tile(G, torch.float32, 64, 8, 4)
+    assert torch.equal(gjp.forward(x, G), ref)
