@@ -243,7 +243,15 @@ def test_forward_64bit_offsets(gjp, oracle_mod, dtype, shape):
         rays = workloads.sample_rays(103, 1500, n_views, n_u, n_v)
         got = y[rays[:, 0], rays[:, 1], rays[:, 2]]
         want = oracle_mod.forward_rays(og, vol, rays)
-        assert_parity(got, want, TOL32)
+        # Element bound: coordinates here reach ~3000 (ray base plus plane
+        # times slope), so each single-precision sample position carries up
+        # to delta ~ 2^-24 * 3000 = 1.8e-4 voxel of rounding. On white noise
+        # (neighbour differences of sd 0.41) a ray of n samples then errs by
+        # about sqrt(n) * 0.41 * delta against a sum of about n / 2, i.e.
+        # 0.82 * delta / sqrt(n) = 2e-5 relative at the shortest compared rays
+        # (n ~ 50); 1e-4 of the largest value is that at 5 sigma. The relative
+        # L2 bound stays the stated 1e-5.
+        assert_parity(got, want, TOL32, elem=1e-4)
 
 
 def test_two_rays_per_lane_64bit_offsets(gjp, oracle_mod):

@@ -286,7 +286,14 @@ def test_full_c2_forward_and_adjoint(gjp, oracle_mod):
     note("c2: adjoint")
     got = gjp.back(y.to(dev), G).cpu().numpy()
     want = oracle_mod.adjoint(og, y.numpy())
-    assert_parity(got, want, 1e-5)
+    # Element bound: at these coordinates (source 1024 voxels out, ray bases
+    # in the hundreds) single-precision sample positions, and so the weights,
+    # err by up to delta ~ 2^-24 * 700 = 4e-5; a voxel sums about 27 terms
+    # (three views, about 3 x 3 rays each) of white-noise values y in [0, 1),
+    # so at random signs |error| ~ sqrt(27) * 2 * delta * 0.5 = 2e-4, about 3e-5
+    # of the largest value (6.6); 1e-4 of it is that at about 3 sigma. The
+    # relative L2 bound stays the stated 1e-5.
+    assert_parity(got, want, 1e-5, elem=1e-4)
 
 
 def test_full_c3_forward(gjp, oracle_mod):
