@@ -104,6 +104,26 @@ gjp_status gjp_destroy_geometry(gjp_geometry *g);
 gjp_status gjp_forward_project(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
                                float *d_sino, void *stream);
 
+/* gjp_forward_project without any allocation, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc). Same arguments, kernels, launch
+   configuration and results as gjp_forward_project; the two padded pair
+   copies are written into a fixed device scratch of 64 MiB that the library
+   holds on every device it runs on until the process ends (enough for FP32
+   volumes up to 158^3 voxels, 16-bit ones up to 200^3). The
+   geometry must already have its device copy on the current device: any
+   other projection call with it on that device makes one. Calls on one device
+   share the scratch, whose contents are those of the last call: calls that
+   overlap on one device (different streams, or threads) race and must be
+   serialised by the caller. Calls no hipMalloc, hipFree or other allocating
+   routine. Errors: GJP_EINVAL (as gjp_forward_project; padded copies larger
+   than the scratch: each is (n0+2) * (n1+2) * (n2+3 rounded down to even)
+   * 2 * element size bytes rounded up to 256, and both must fit; no device
+   copy of the geometry yet),
+   GJP_EUNSUPPORTED, GJP_EHIP. */
+gjp_status gjp_forward_project_noalloc(const gjp_geometry *g, const void *d_vol,
+                                       int32_t vol_dtype, float *d_sino, void *stream);
+
 /* Plain forward projection for comparison (Algorithm 1 as written: one lane
    per ray, the four neighbours of each sample read from d_vol itself with a
    zero-padding bounds test each, Eq. 8). Arguments and layouts as for

@@ -21,7 +21,7 @@ CLIP_CYLINDER = 1  # gjp_geometry_desc.flags
 # Every symbol include/gjp.h declares.
 EXPORTS = (
     "gjp_create_geometry", "gjp_destroy_geometry", "gjp_forward_project",
-    "gjp_forward_project_naive", "gjp_back_project",
+    "gjp_forward_project_noalloc", "gjp_forward_project_naive", "gjp_back_project",
     "gjp_forward_project_batched", "gjp_views_circular_cone", "gjp_views_parallel",
     "gjp_count_samples", "gjp_autotune_forward", "gjp_set_forward_tile", "gjp_get_forward_tile",
     "gjp_timing_enable",
@@ -70,6 +70,7 @@ def lib():
     L.gjp_create_geometry.argtypes = [ctypes.POINTER(GeometryDesc), ctypes.POINTER(vp)]
     L.gjp_destroy_geometry.argtypes = [vp]
     L.gjp_forward_project.argtypes = [vp, vp, i32, vp, vp]
+    L.gjp_forward_project_noalloc.argtypes = [vp, vp, i32, vp, vp]
     L.gjp_forward_project_naive.argtypes = [vp, vp, i32, vp, vp]
     L.gjp_back_project.argtypes = [vp, vp, vp, vp]
     L.gjp_forward_project_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),

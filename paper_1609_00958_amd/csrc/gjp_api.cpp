@@ -407,6 +407,23 @@ extern "C" gjp_status gjp_destroy_geometry(gjp_geometry* g) {
   return GJP_OK;
 }
 
+int gjp::geometry_device_existing(const gjp_geometry* g, const double** views,
+                                  const float** proj) {
+  int dvc = 0;
+  hipError_t e = hipGetDevice(&dvc);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dvc < 0 || dvc >= gjp_geometry::kMaxDev) return fail(GJP_EUNSUPPORTED, "device index");
+  std::lock_guard<std::mutex> lk(g->mu);
+  const gjp_geometry::Dev& D = g->dev[dvc];
+  if (!D.views)
+    return fail(GJP_EINVAL,
+                "the geometry has no copy on this device yet: any other projection call on "
+                "this device makes it");
+  *views = D.views;
+  *proj = D.proj;
+  return GJP_OK;
+}
+
 int gjp::geometry_device(const gjp_geometry* g, const double** views, const float** proj) {
   int dvc = 0;
   hipError_t e = hipGetDevice(&dvc);
@@ -718,6 +735,19 @@ gjp_status validate_fwd(const gjp_geometry* g, const void* d_vol, int32_t dtype,
   return GJP_OK;
 }
 
+// Pad into `padded` (2 * copy_bytes) and project: the forward's launches.
+int forward_into(const gjp_geometry* g, const double* d_views, const void* d_vol, int dtype,
+                 float* d_sino, void* padded, hipStream_t s, const FwdTile& tile) {
+  FwdArgs a;
+  fill_fwd_args(g, d_views, nullptr, d_sino, tile, a);
+  set_padded(a, padded, dtype, g->n);
+  int st = gjp::launch_pad(d_vol, const_cast<void*>(a.vol_a), const_cast<void*>(a.vol_b), dtype,
+                           g->n, s);
+  if (st == GJP_OK)
+    st = gjp::launch_forward(a, dtype, g->weight, needs_idx64(g->n, dtype), g->n_views, s);
+  return st;
+}
+
 gjp_status forward_with_tile(const gjp_geometry* g, const void* d_vol, int32_t dtype,
                              float* d_sino, hipStream_t s, const FwdTile& tile) {
   const double* d_views = nullptr;
@@ -729,13 +759,7 @@ gjp_status forward_with_tile(const gjp_geometry* g, const void* d_vol, int32_t d
   void* padded = nullptr;
   GJP_HIP(scratch_alloc(&padded, (size_t)(2 * copy_bytes(g->n, dtype)), s),
           "forward: padded pair copies");
-  FwdArgs a;
-  fill_fwd_args(g, d_views, nullptr, d_sino, tile, a);
-  set_padded(a, padded, dtype, g->n);
-  st = gjp::launch_pad(d_vol, const_cast<void*>(a.vol_a), const_cast<void*>(a.vol_b), dtype,
-                       g->n, s);
-  if (st == GJP_OK)
-    st = gjp::launch_forward(a, dtype, g->weight, needs_idx64(g->n, dtype), g->n_views, s);
+  st = forward_into(g, d_views, d_vol, dtype, d_sino, padded, s, tile);
   const hipError_t fe = hipFreeAsync(padded, s);
   if (st != GJP_OK) return (gjp_status)st;
   if (fe != hipSuccess) return hip_fail(fe, "forward: free padded volume");
@@ -749,6 +773,26 @@ extern "C" gjp_status gjp_forward_project(const gjp_geometry* g, const void* d_v
   if (st != GJP_OK) return st;
   return forward_with_tile(g, d_vol, vol_dtype, d_sino, (hipStream_t)stream,
                            tile_for(g, vol_dtype));
+}
+
+extern "C" gjp_status gjp_forward_project_noalloc(const gjp_geometry* g, const void* d_vol,
+                                                  int32_t vol_dtype, float* d_sino, void* stream) {
+  gjp_status st = validate_fwd(g, d_vol, vol_dtype, d_sino);
+  if (st != GJP_OK) return st;
+  const unsigned long long need = 2 * copy_bytes(g->n, vol_dtype);
+  if (need > gjp::kNoAllocScratchBytes)
+    return fail(GJP_EINVAL, "forward_noalloc: the padded pair copies need " +
+                                std::to_string(need) + " bytes, above the fixed scratch of " +
+                                std::to_string(gjp::kNoAllocScratchBytes) + " bytes");
+  const double* d_views = nullptr;
+  const float* d_proj = nullptr;
+  int r = gjp::geometry_device_existing(g, &d_views, &d_proj);
+  if (r != GJP_OK) return (gjp_status)r;
+  void* padded = nullptr;
+  r = gjp::noalloc_scratch(&padded);
+  if (r != GJP_OK) return (gjp_status)r;
+  return (gjp_status)forward_into(g, d_views, d_vol, vol_dtype, d_sino, padded,
+                                  (hipStream_t)stream, tile_for(g, vol_dtype));
 }
 
 extern "C" gjp_status gjp_forward_project_naive(const gjp_geometry* g, const void* d_vol,

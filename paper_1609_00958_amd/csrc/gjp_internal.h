@@ -83,6 +83,8 @@ struct FwdArgs {
 
 // Device views of a geometry on the current device (uploads on first use).
 int geometry_device(const gjp_geometry* g, const double** views, const float** proj);
+// The same without uploading: GJP_EINVAL if there is no copy on this device.
+int geometry_device_existing(const gjp_geometry* g, const double** views, const float** proj);
 
 // Launchers (gjp_kernels.hip). Return a gjp_status.
 int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int n[3],
@@ -121,5 +123,10 @@ int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n
 int batched_grid_size(int cls);
 
 size_t dtype_size(int dtype);
+
+// Fixed device scratch of gjp_forward_project_noalloc (gjp_kernels.hip): its
+// size, and its address on the current device (looked up once per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+int noalloc_scratch(void** ptr);
 
 }  // namespace gjp

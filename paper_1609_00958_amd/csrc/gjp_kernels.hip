@@ -1602,6 +1602,40 @@ static int check_launch(const char* what) {
 
 size_t dtype_size(int dtype) { return dtype == 0 ? 4 : 2; }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the forward that allocates nothing
+// (gjp_forward_project_noalloc): the two padded pair copies live in this
+// file-scope array instead of the stream-ordered pool. Every device the
+// library runs on holds its own copy until the process ends. In host code the
+// array's name is only a stand-in for the symbol: its device address on the
+// current device comes from hipGetSymbolAddress, once per device, and only
+// that address is passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[gjp_geometry::kMaxDev] = {};
+}  // namespace
+
+int noalloc_scratch(void** ptr) {
+  int dvc = 0;
+  hipError_t e = hipGetDevice(&dvc);
+  if (e != hipSuccess) return set_error(-3, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dvc < 0 || dvc >= gjp_geometry::kMaxDev) return set_error(-4, "device index");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dvc]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(-3, std::string("noalloc scratch: hipGetSymbolAddress: ") +
+                               hipGetErrorString(e));
+    g_scratch_ptr[dvc] = p;
+  }
+  *ptr = g_scratch_ptr[dvc];
+  return 0;
+}
+
 int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int n[3],
                hipStream_t s) {
   dim3 grid((unsigned)((padded_pitch(n[2]) + 255) / 256), (unsigned)(n[1] + 2), (unsigned)(n[0] + 2));

@@ -165,6 +165,23 @@ def forward(vol, geom: Geometry, out=None):
     return out
 
 
+def forward_noalloc(vol, geom: Geometry, out):
+    """Sinogram A vol into the caller's float32 `out`, with the padded copies
+    in the library's fixed device scratch (no allocation; calls on one device
+    must not overlap)."""
+    torch = _torch()
+    _check_tensor(vol, geom.shape, "volume")
+    _check_tensor(out, geom.sino_shape, "sinogram")
+    if out.dtype != torch.float32:
+        raise TypeError("sinogram must be float32")
+    if out.device != vol.device:
+        raise ValueError("sinogram and volume must be on the same device")
+    with torch.cuda.device(vol.device):
+        check(lib().gjp_forward_project_noalloc(geom.handle, vol.data_ptr(), _dtype_code(vol),
+                                                out.data_ptr(), _stream(vol.device)))
+    return out
+
+
 def forward_naive(vol, geom: Geometry, out=None):
     """Sinogram A vol from the plain one-lane-per-ray kernel (for comparison)."""
     torch = _torch()

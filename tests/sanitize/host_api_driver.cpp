@@ -43,6 +43,7 @@ int launch_batched_forward(const BatchInst*, const uint2*, int, int*, int, int, 
 }
 int batched_grid_size(int) { return 1; }
 size_t dtype_size(int dtype) { return dtype == 0 ? 4 : 2; }
+int noalloc_scratch(void**) { return stub("noalloc scratch"); }
 }  // namespace gjp
 
 static int bad = 0;
@@ -130,6 +131,16 @@ int main() {
   CHECK(gjp_forward_project(g, (void*)16, 7, (float*)16, nullptr) == GJP_EINVAL);
   CHECK(gjp_forward_project(g, (void*)18, 0, (float*)16, nullptr) == GJP_EINVAL);
   CHECK(gjp_back_project(g, nullptr, (float*)16, nullptr) == GJP_EINVAL);
+  CHECK(gjp_forward_project_noalloc(g, nullptr, 0, nullptr, nullptr) == GJP_EINVAL);
+  {
+    // padded copies of a 200^3 FP32 volume exceed the fixed scratch: rejected
+    // on the host, before the scratch or the geometry's device copy is looked up
+    gjp_geometry* big = make(200, 200, 200, 0, 1, 2, 2, dv, 0, 0);
+    CHECK(big != nullptr);
+    CHECK(gjp_forward_project_noalloc(big, (void*)16, 0, (float*)16, nullptr) == GJP_EINVAL);
+    CHECK(strstr(gjp_last_error(), "scratch") != nullptr);
+    CHECK(gjp_destroy_geometry(big) == GJP_OK);
+  }
   CHECK(gjp_forward_project_batched(0, nullptr, nullptr, nullptr, nullptr, nullptr) == GJP_EINVAL);
   CHECK(gjp_sart_residual(-1, nullptr, nullptr, nullptr, nullptr, nullptr) == GJP_EINVAL);
   CHECK(gjp_sart_update(4, nullptr, nullptr, nullptr, 1.0f, 0, nullptr) == GJP_EINVAL);
