@@ -1081,123 +1081,42 @@ __device__ __forceinline__ void pair_weights(float fplane, float g, float c, flo
   }
 }
 
-// Weights of one sample for the voxels z and z + 1 of an interior pair
-// (1 <= z and z + 1 <= n - 2): the linear tents without the clamp of the
-// coordinate. A coordinate the clamp would move (below -1, or at or above the
-// largest float below n) lies two or more voxels from both, where the clamped
-// and the unclamped tents are both zero; inside, the values are those of
-// pair_weights. Other weights: the clamped form.
-template <int WF>
-__device__ __forceinline__ void pair_weights_interior(float fplane, float g, float c, float hz,
-                                                      float fz, int z, float& b0, float& b1) {
-  if constexpr (WF == W_LINEAR) {
-    const float s0 = __builtin_fmaf(fplane, g, c) - fz;
-    b0 = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(s0), 0.0f, 1.0f);
-    b1 = __builtin_amdgcn_fmed3f(s0, 2.0f - s0, 0.0f);
-  } else {
-    pair_weights<WF>(fplane, g, c, hz, fz, z, b0, b1);
-  }
-}
-
-typedef float f3v __attribute__((ext_vector_type(3)));
-
-// NC candidate rays of one detector column, from table entry vo / 16 of the
-// column at byte offset `so` of the table resource, each loaded once and
-// evaluated on the two planes p0 and p0 + 1 for the voxel pair (z, z + 1):
-// sums s<plane><z>.
-// CHECK: each sample is tested against its ray's plane range (the forward's
-// double-precision range) with the clamped weights: exact for every voxel and
-// for clipped ranges. Otherwise (interior voxels, unclipped ranges) the range
-// test is left out and only the 12 bytes {c_b, g_b, y * scale} of an entry
-// are loaded: a plane outside a ray's range has its sample outside the
-// zero-padded domain on a transverse axis (in double precision, and in single
-// precision within far less than a voxel), so its weight is exactly zero on
-// the axis-2 voxels 1 .. n - 2 and, through the column's in-plane weights, on
-// the rows 1 .. n - 2.
-template <int WF, int NC, bool CHECK>
-__device__ __forceinline__ void block_candidates(__amdgpu_buffer_rsrc_t rt, uint32_t vo,
-                                                 uint32_t so, int p0, float fp0, float hz,
-                                                 float fz, int z, float& s00, float& s01,
-                                                 float& s10, float& s11) {
-  if constexpr (CHECK) {
-    f4v rr[NC];
+// NC candidate rays R[iv_lo .. iv_lo + NC), each loaded once and evaluated on
+// the two planes p0 and p0 + 1 for the voxel pair (z, z + 1): sums s<plane><z>.
+template <int WF, int NC>
+__device__ __forceinline__ void block_candidates(const float4* __restrict__ R, int iv_lo, int p0,
+                                                 float fp0, float hz, float fz, int z,
+                                                 float& s00, float& s01, float& s10,
+                                                 float& s11) {
+  float4 rr[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
-      rr[k] = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rt, vo + 16u * k, so, 0));
+  for (int k = 0; k < NC; ++k) rr[k] = R[iv_lo + k];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const f4v r = rr[k];
-      const uint32_t mr = __float_as_uint(r.x);
-      const int i0 = (int)((mr >> 2) & 0x7fffu);
-      const int i1 = (int)(mr >> 17);
-      float b0, b1;
-      pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, b0, b1);
-      const float wy0 = (p0 >= i0 && p0 < i1) ? r.w : 0.0f;
-      s00 = __builtin_fmaf(wy0, b0, s00);
-      s01 = __builtin_fmaf(wy0, b1, s01);
-      pair_weights<WF>(fp0 + 1.0f, r.z, r.y, hz, fz, z, b0, b1);
-      const float wy1 = (p0 + 1 >= i0 && p0 + 1 < i1) ? r.w : 0.0f;
-      s10 = __builtin_fmaf(wy1, b0, s10);
-      s11 = __builtin_fmaf(wy1, b1, s11);
-    }
-  } else {
-    f3v rr[NC];
-#pragma unroll
-    for (int k = 0; k < NC; ++k)
-      rr[k] = __builtin_bit_cast(f3v,
-                                 __builtin_amdgcn_raw_buffer_load_b96(rt, vo + 16u * k + 4u, so, 0));
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const f3v r = rr[k];  // {c_b, g_b, y * scale}
-      float b0, b1;
-      pair_weights_interior<WF>(fp0, r.y, r.x, hz, fz, z, b0, b1);
-      s00 = __builtin_fmaf(r.z, b0, s00);
-      s01 = __builtin_fmaf(r.z, b1, s01);
-      pair_weights_interior<WF>(fp0 + 1.0f, r.y, r.x, hz, fz, z, b0, b1);
-      s10 = __builtin_fmaf(r.z, b0, s10);
-      s11 = __builtin_fmaf(r.z, b1, s11);
-    }
-  }
-}
-
-// Candidate rays iv_lo .. iv_hi of one column, per lane, each tested against
-// its plane range (long or unbounded candidate windows).
-template <int WF>
-__device__ __forceinline__ void lane_candidates(__amdgpu_buffer_rsrc_t rt, uint32_t so, int iv_lo,
-                                                int iv_hi, int p0, float fp0, float hz, float fz,
-                                                int z, float& s00, float& s01, float& s10,
-                                                float& s11) {
-  for (int iv = iv_lo; iv <= iv_hi; ++iv) {
-    const f4v r = __builtin_bit_cast(f4v,
-                                     __builtin_amdgcn_raw_buffer_load_b128(rt, 16u * (uint32_t)iv, so, 0));
+  for (int k = 0; k < NC; ++k) {
+    const float4 r = rr[k];
     const uint32_t mr = __float_as_uint(r.x);
     const int i0 = (int)((mr >> 2) & 0x7fffu);
     const int i1 = (int)(mr >> 17);
-    float c0, c1;
-    if (p0 >= i0 && p0 < i1) {
-      pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, c0, c1);
-      s00 = __builtin_fmaf(r.w, c0, s00);
-      s01 = __builtin_fmaf(r.w, c1, s01);
-    }
-    if (p0 + 1 >= i0 && p0 + 1 < i1) {
-      pair_weights<WF>(fp0 + 1.0f, r.z, r.y, hz, fz, z, c0, c1);
-      s10 = __builtin_fmaf(r.w, c0, s10);
-      s11 = __builtin_fmaf(r.w, c1, s11);
-    }
+    float b0, b1;
+    pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, b0, b1);
+    const float wy0 = (p0 >= i0 && p0 < i1) ? r.w : 0.0f;
+    s00 = __builtin_fmaf(wy0, b0, s00);
+    s01 = __builtin_fmaf(wy0, b1, s01);
+    pair_weights<WF>(fp0 + 1.0f, r.z, r.y, hz, fz, z, b0, b1);
+    const float wy1 = (p0 + 1 >= i0 && p0 + 1 < i1) ? r.w : 0.0f;
+    s10 = __builtin_fmaf(wy1, b0, s10);
+    s11 = __builtin_fmaf(wy1, b1, s11);
   }
 }
 
 // Workgroup placement of the gather: a lane owns a 2 x 2 x 2 voxel block
-// (x, x+1) x (y, y+1) x (z, z+1); a wavefront covers 64 such blocks along
-// axis 2 and a workgroup four wavefronts along y (8 rows). Logical workgroup
+// (x, x+1) x (y, y+1) x (z, z+1); a wavefront covers 128 voxels along axis 2
+// and a workgroup four such wavefronts along y (8 rows). Logical workgroup
 // indices are ordered in tiles of GTX x-pairs by GTY row blocks (axis-2 blocks
 // fastest), and each XCD walks one contiguous range of them, so the
 // workgroups resident on an XCD cover a compact (x, y) region whose rays come
 // from a few detector columns per view: the ray table they read stays in that
-// XCD's L2. Along axis 2, lane L of the nzb * 64 lanes of a line takes block
-// (L - 32) mod (nzb * 64): the first wavefront holds both the lowest and the
-// highest blocks (when the line's block count is a multiple of 64), so the
-// other wavefronts hold interior voxels only.
+// XCD's L2.
 constexpr int GTX = 8, GTY = 4;
 
 __host__ __device__ inline void gather_grid(const int* n, int& nzb, int& nyb, int& ntx, int& nty) {
@@ -1205,138 +1124,6 @@ __host__ __device__ inline void gather_grid(const int* n, int& nzb, int& nyb, in
   nyb = (n[1] + 7) / 8;
   ntx = ((n[0] + 1) / 2 + GTX - 1) / GTX;
   nty = (nyb + GTY - 1) / GTY;
-}
-
-// Constants of one (view, driving axis) for a wavefront's block.
-struct GatherAxis {
-  int m;           // driving axis (0 or 1)
-  int va;          // first of the two in-plane rows
-  int p0;          // first of the two planes
-  float fva, ha;   // va as a float, upper clamp of the in-plane coordinate
-  float fp0;       // p0 as a float
-  bool two;        // plane p0 + 1 exists
-  // projective rows: terms of the two planes and coefficients of the
-  // in-plane coordinate (u and w rows of the detector map)
-  float KA0, KA1, KW0, KW1, PaA, PaW, P6;
-};
-
-// All candidate columns iu_lo .. iu_hi of one view and driving axis, in
-// chunks of 64. Lane k first evaluates column iu0 + k of the chunk: its
-// in-plane weights for the block's two planes and rows, the affine map from
-// the axis-2 coordinate to the detector v coordinate on both planes, and a
-// bound on the candidate rays per lane (window length at the two ends of the
-// wavefront's axis-2 hull; the length is convex in z). Those values are
-// wave-uniform per column; the column loop then takes them from the
-// wavefront's LDS slots (broadcast reads) and only the per-lane window start
-// and the candidate rays remain per lane.
-template <int WF, bool CHECK>
-__device__ __forceinline__ void gather_columns(
-    const GatherAxis& X, const float4* __restrict__ C, __amdgpu_buffer_rsrc_t rt,
-    uint32_t view_off, int pitch, int n_v, int iu_lo, int iu_hi, float zq_lo, float zq_hi,
-    float zlo_w, float zhi_w, float fz, float hz, int z, bool zin, float4* slots,
-    float (&acc)[8]) {
-  const float e = 0.002f;       // widened neighbourhood (voxels)
-  const float margin = 0.05f;   // widened ranges (pixels)
-  const int lane = (int)(threadIdx.x & 63);
-  const float fp1 = X.fp0 + 1.0f;
-  // the window's lower and upper ends at axis-2 position zz are taken at
-  // zz + dlo and zz + dhi (the v map's slope has the sign of P6 on both planes)
-  const float dlo = X.P6 >= 0.0f ? -1.0f - e : 2.0f + e;
-  const float dhi = X.P6 >= 0.0f ? 2.0f + e : -1.0f - e;
-  for (int cb = iu_lo; cb <= iu_hi; cb += 64) {
-    const int iu = cb + lane;
-    bool act = iu <= iu_hi;
-    float4 col = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (act) col = C[iu];
-    act = act && (int)__float_as_uint(col.x) == X.m;
-    // in-plane weights w<plane><row> (rows va, va + 1; va is even, as z is,
-    // so the tents reproduce the forward's weights exactly)
-    float w00, w01, w10, w11;
-    pair_weights<WF>(X.fp0, col.z, col.y, X.ha, X.fva, X.va, w00, w01);
-    pair_weights<WF>(fp1, col.z, col.y, X.ha, X.fva, X.va, w10, w11);
-    if (!X.two) {
-      w10 = 0.0f;
-      w11 = 0.0f;
-    }
-    act = act && !(w00 == 0.0f && w01 == 0.0f && w10 == 0.0f && w11 == 0.0f);
-    // v of the column's rays on each plane: (A + P6 z) / W, affine in z
-    const float pa0 = __builtin_fmaf(X.fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
-    const float A0 = __builtin_fmaf(X.PaA, pa0, X.KA0), W0 = __builtin_fmaf(X.PaW, pa0, X.KW0);
-    const float A1 = __builtin_fmaf(X.PaA, pa1, X.KA1), W1 = __builtin_fmaf(X.PaW, pa1, X.KW1);
-    int nc = 0;  // 0: unbounded window (every ray of the column)
-    float sl0 = 0.0f, b0 = 0.0f, sl1 = 0.0f, b1 = 0.0f;
-    if (W0 > 1.0e-6f && W1 > 1.0e-6f) {
-      const float inv0 = __builtin_amdgcn_rcpf(W0), inv1 = __builtin_amdgcn_rcpf(W1);
-      sl0 = X.P6 * inv0;  // pixels per voxel along z
-      sl1 = X.P6 * inv1;
-      b0 = A0 * inv0;
-      b1 = A1 * inv1;
-      // rays whose axis-2 coordinate lies in [zz - 1, zz + 2) on either
-      // plane; an interval of length L holds at most floor(L) + 1 integers
-      auto len = [&](float zz) {
-        const float lo = fminf(__builtin_fmaf(sl0, zz + dlo, b0), __builtin_fmaf(sl1, zz + dlo, b1));
-        const float hi = fmaxf(__builtin_fmaf(sl0, zz + dhi, b0), __builtin_fmaf(sl1, zz + dhi, b1));
-        return hi - lo + 2.0f * margin;
-      };
-      nc = (int)(fmaxf(len(zlo_w), len(zhi_w)) + 1.0e-3f) + 1;
-    }
-    slots[lane] = make_float4(w00, w01, w10, w11);
-    slots[64 + lane] = make_float4(sl0, b0 - margin, sl1, b1 - margin);
-    __builtin_amdgcn_wave_barrier();
-    uint64_t live = __ballot(act);
-    while (live) {
-      const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(live));
-      live &= live - 1;
-      const int nck = __builtin_amdgcn_readlane(nc, k);
-      const float4 wA = slots[k];
-      const float4 wz = slots[64 + k];
-      const uint32_t so = view_off + (uint32_t)(cb + k) * (uint32_t)pitch * 16u;
-      float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
-      if (nck >= 1 && nck <= 8) {
-        const float lo = fminf(__builtin_fmaf(wz.x, zq_lo, wz.y), __builtin_fmaf(wz.z, zq_lo, wz.w));
-        int iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
-        if (!zin) iv_lo = n_v;  // reads the column's empty entries only
-        const uint32_t vo = 16u * (uint32_t)iv_lo;
-        switch (nck) {
-          case 1:
-          case 2: block_candidates<WF, 2, CHECK>(rt, vo, so, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 3: block_candidates<WF, 3, CHECK>(rt, vo, so, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 4: block_candidates<WF, 4, CHECK>(rt, vo, so, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 5: block_candidates<WF, 5, CHECK>(rt, vo, so, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 6: block_candidates<WF, 6, CHECK>(rt, vo, so, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 7: block_candidates<WF, 7, CHECK>(rt, vo, so, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11); break;
-          default: block_candidates<WF, 8, CHECK>(rt, vo, so, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11); break;
-        }
-      } else {
-        // long or unbounded candidate windows: an explicit per-lane loop
-        int iv_lo = 0, iv_hi = n_v - 1;
-        if (nck != 0) {
-          const float lo = fminf(__builtin_fmaf(wz.x, zq_lo, wz.y), __builtin_fmaf(wz.z, zq_lo, wz.w));
-          const float hi = fmaxf(__builtin_fmaf(wz.x, zq_hi, wz.y), __builtin_fmaf(wz.z, zq_hi, wz.w)) +
-                           2.0f * margin;
-          iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
-          iv_hi = min(n_v - 1, (int)floorf(fminf(hi, (float)n_v)));
-        }
-        if (!zin) iv_hi = iv_lo - 1;
-        lane_candidates<WF>(rt, so, iv_lo, iv_hi, X.p0, X.fp0, hz, fz, z, s00, s01, s10, s11);
-      }
-      // block voxel (plane p0 + d, row va + r, z + k) gets wA<d><r> s<d><k>;
-      // acc index = 4 X + 2 Y + Z for voxel (x + X, y + Y, z + Z)
-      if (X.m == 0) {
-        acc[0] = __builtin_fmaf(wA.x, s00, acc[0]); acc[1] = __builtin_fmaf(wA.x, s01, acc[1]);
-        acc[2] = __builtin_fmaf(wA.y, s00, acc[2]); acc[3] = __builtin_fmaf(wA.y, s01, acc[3]);
-        acc[4] = __builtin_fmaf(wA.z, s10, acc[4]); acc[5] = __builtin_fmaf(wA.z, s11, acc[5]);
-        acc[6] = __builtin_fmaf(wA.w, s10, acc[6]); acc[7] = __builtin_fmaf(wA.w, s11, acc[7]);
-      } else {
-        acc[0] = __builtin_fmaf(wA.x, s00, acc[0]); acc[1] = __builtin_fmaf(wA.x, s01, acc[1]);
-        acc[4] = __builtin_fmaf(wA.y, s00, acc[4]); acc[5] = __builtin_fmaf(wA.y, s01, acc[5]);
-        acc[2] = __builtin_fmaf(wA.z, s10, acc[2]); acc[3] = __builtin_fmaf(wA.z, s11, acc[3]);
-        acc[6] = __builtin_fmaf(wA.w, s10, acc[6]); acc[7] = __builtin_fmaf(wA.w, s11, acc[7]);
-      }
-    }
-    // every lane has read the slots before the next chunk rewrites them
-    __builtin_amdgcn_wave_barrier();
-  }
 }
 
 // The two planes of a lane's block along the driving axis m, each with the
@@ -1348,7 +1135,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
     const float4* __restrict__ rays, const float4* __restrict__ cols,
     const int* __restrict__ mask, int view0, int c0, int n_chunk, int accumulate,
     float* __restrict__ vol) {
-  __shared__ float4 s_cols[4][128];
   int nzb, nyb, ntx, nty;
   gather_grid(G.n, nzb, nyb, ntx, nty);
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
@@ -1363,60 +1149,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
   if (x >= G.n[0] || yb >= nyb) return;
   const int y = yb * 8 + 2 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (y >= G.n[1]) return;
-  const int lane = (int)(threadIdx.x & 63);
-  const int span = 64 * nzb;
-  int blk = zb * 64 + lane - 32;
-  if (blk < 0) blk += span;
-  const int z = 2 * blk;
+  const int z = 2 * (zb * 64 + (int)(threadIdx.x & 63));
   const bool zin = z < G.n[2];
-  // the wavefront's axis-2 hull (blocks with voxels); none: nothing to do
-  const int zlo_i = __builtin_amdgcn_readfirstlane(wave_min(zin ? z : 0x7fffffff));
-  const int zhi_i = __builtin_amdgcn_readfirstlane(wave_max(zin ? z : -1));
-  if (zhi_i < 0) return;
-  // voxels 0 and n2 - 1 take the checked candidate path
-  const bool z_edge = zlo_i == 0 || zhi_i + 2 >= G.n[2];
   const float fz = (float)z;
-  const float zlo_w = (float)zlo_i, zhi_w = (float)zhi_i;
   const float hz = G.hi[2];
   const float e = 0.002f;       // widened neighbourhood (voxels)
   const float margin = 0.05f;   // widened ranges (pixels)
   const int pitch = n_v + kColumnPad;  // table entries per detector column
-  float4* slots = s_cols[threadIdx.x >> 6];
-  // the table of this launch's views as one buffer resource (below 4 GiB)
-  const float4* T0 = rays + (size_t)c0 * n_u * pitch;
-  const __amdgpu_buffer_rsrc_t rt = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<float4*>(T0), (short)0,
-      (int)(uint32_t)((size_t)n_chunk * n_u * pitch * sizeof(float4)), 0x00020000);
-  // acc[4 X + 2 Y + Z]: voxel (x + X, y + Y, z + Z)
-  float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  // acc_XYZ: voxel (x + X, y + Y, z + Z)
+  float acc000 = 0.0f, acc001 = 0.0f, acc010 = 0.0f, acc011 = 0.0f;
+  float acc100 = 0.0f, acc101 = 0.0f, acc110 = 0.0f, acc111 = 0.0f;
   for (int c = c0; c < c0 + n_chunk; ++c) {
     const int mk = mask[c];
     if (!mk) continue;
     const float* P = proj + 12 * (size_t)(view0 + c);
     const float4* C = cols + (size_t)c * n_u;
-    const uint32_t view_off = (uint32_t)(c - c0) * (uint32_t)n_u * (uint32_t)pitch * 16u;
-    const float P6 = P[6];
-    const float zq_lo = fz + (P6 >= 0.0f ? -1.0f - e : 2.0f + e);
-    const float zq_hi = fz + (P6 >= 0.0f ? 2.0f + e : -1.0f - e);
+    const float4* RY = rays + (size_t)c * n_u * pitch;
     for (int m = 0; m < 2; ++m) {
       if (!(mk & (1 << m))) continue;
-      GatherAxis X;
-      X.m = m;
-      X.va = (m == 0) ? y : x;
-      X.fva = (float)X.va;
-      X.ha = (m == 0) ? G.hi[1] : G.hi[0];
-      X.p0 = (m == 0) ? x : y;
-      X.fp0 = (float)X.p0;
-      X.two = X.p0 + 1 < G.n[m];
-      const int n_a = (m == 0) ? G.n[1] : G.n[0];
-      const float fp1 = X.fp0 + 1.0f;
+      const int va = (m == 0) ? y : x;  // first of the two in-plane rows
+      const float fva = (float)va;
+      const float ha = (m == 0) ? G.hi[1] : G.hi[0];
+      const int p0 = (m == 0) ? x : y;  // first of the two planes
+      const float fp0 = (float)p0, fp1 = fp0 + 1.0f;
+      const bool two = p0 + 1 < G.n[m];
       // candidate columns: u of (plane, va - (1 + e)) and (plane, va + 1 + (1 + e))
       // on both planes
-      const float qa0 = X.fva - 1.0f - e, qa1 = X.fva + 2.0f + e;
+      const float qa0 = fva - 1.0f - e, qa1 = fva + 2.0f + e;
       int iu_lo = n_u, iu_hi = -1;
       bool iu_all = false;
       for (int dp = 0; dp < 2; ++dp) {
-        const float fpl = dp ? fp1 : X.fp0;
+        const float fpl = dp ? fp1 : fp0;
         const float qx0 = (m == 0) ? fpl : qa0, qy0 = (m == 0) ? qa0 : fpl;
         const float qx1 = (m == 0) ? fpl : qa1, qy1 = (m == 0) ? qa1 : fpl;
         const float un0 = __builtin_fmaf(P[0], qx0, __builtin_fmaf(P[1], qy0, P[3]));
@@ -1435,28 +1198,110 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
         iu_lo = 0;
         iu_hi = n_u - 1;
       }
-      if (iu_lo > iu_hi) continue;
       // the projective rows' terms in the driving coordinate (fixed per plane)
-      // and their coefficients of the in-plane coordinate (the window is a
-      // bound with margins, so this order of rounding is free)
-      const float PfA = (m == 0) ? P[4] : P[5];
-      const float PfW = (m == 0) ? P[8] : P[9];
-      X.PaA = (m == 0) ? P[5] : P[4];
-      X.PaW = (m == 0) ? P[9] : P[8];
-      X.KA0 = __builtin_fmaf(PfA, X.fp0, P[7]);
-      X.KA1 = __builtin_fmaf(PfA, fp1, P[7]);
-      X.KW0 = __builtin_fmaf(PfW, X.fp0, P[11]);
-      X.KW1 = __builtin_fmaf(PfW, fp1, P[11]);
-      X.P6 = P6;
-      // the range test can be left out where every voxel of the wavefront's
-      // blocks is interior on both transverse axes and ranges are not clipped
-      const bool check = G.clip || z_edge || X.va < 1 || X.va + 1 > n_a - 2;
-      if (check)
-        gather_columns<WF, true>(X, C, rt, view_off, pitch, n_v, iu_lo, iu_hi, zq_lo, zq_hi,
-                                 zlo_w, zhi_w, fz, hz, z, zin, slots, acc);
-      else
-        gather_columns<WF, false>(X, C, rt, view_off, pitch, n_v, iu_lo, iu_hi, zq_lo, zq_hi,
-                                  zlo_w, zhi_w, fz, hz, z, zin, slots, acc);
+      // and their coefficients of the in-plane coordinate (the window below
+      // is a bound with margins, so this order of rounding is free)
+      const float PfA = (m == 0) ? P[4] : P[5], PaA = (m == 0) ? P[5] : P[4];
+      const float PfW = (m == 0) ? P[8] : P[9], PaW = (m == 0) ? P[9] : P[8];
+      const float KA0 = __builtin_fmaf(PfA, fp0, P[7]), KA1 = __builtin_fmaf(PfA, fp1, P[7]);
+      const float KW0 = __builtin_fmaf(PfW, fp0, P[11]), KW1 = __builtin_fmaf(PfW, fp1, P[11]);
+      for (int iu = iu_lo; iu <= iu_hi; ++iu) {
+        const float4 col = C[iu];
+        if ((int)__float_as_uint(col.x) != m) continue;
+        // in-plane weights wA<plane><row> (rows va, va + 1; va is even, as z
+        // is, so the tents reproduce the forward's weights exactly)
+        float wA00, wA01, wA10, wA11;
+        pair_weights<WF>(fp0, col.z, col.y, ha, fva, va, wA00, wA01);
+        pair_weights<WF>(fp1, col.z, col.y, ha, fva, va, wA10, wA11);
+        if (!two) {
+          wA10 = 0.0f;
+          wA11 = 0.0f;
+        }
+        if (wA00 == 0.0f && wA01 == 0.0f && wA10 == 0.0f && wA11 == 0.0f) continue;
+        // v of the column's rays on each plane: (A + P6 z) / W, affine in z;
+        // A and W are the plane terms (per axis) plus the column's in-plane term
+        const float pa0 = __builtin_fmaf(fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
+        const float A0 = __builtin_fmaf(PaA, pa0, KA0), W0 = __builtin_fmaf(PaW, pa0, KW0);
+        const float A1 = __builtin_fmaf(PaA, pa1, KA1), W1 = __builtin_fmaf(PaW, pa1, KW1);
+        const float4* R = RY + (size_t)iu * pitch;
+        float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
+        int nc = 0;  // wave-uniform bound on the candidates per lane
+        float win_hi = 3.0e38f;  // upper end of the lane's window (none: every ray)
+        int iv_lo = 0, iv_hi = n_v - 1;
+        if (W0 > 1.0e-6f && W1 > 1.0e-6f) {
+          // rays whose axis-2 coordinate lies in [z - 1, z + 2) on either plane
+          const float inv0 = __builtin_amdgcn_rcpf(W0), inv1 = __builtin_amdgcn_rcpf(W1);
+          const float sl0 = P[6] * inv0, sl1 = P[6] * inv1;  // pixels per voxel along z
+          const float b0 = A0 * inv0, b1 = A1 * inv1;
+          // span of the union window at axis-2 position zz (convex in zz)
+          auto window = [&](float zz, float& lo, float& hi) {
+            const float a0 = __builtin_fmaf(sl0, zz - 1.0f - e, b0);
+            const float a1 = __builtin_fmaf(sl0, zz + 2.0f + e, b0);
+            const float c0 = __builtin_fmaf(sl1, zz - 1.0f - e, b1);
+            const float c1 = __builtin_fmaf(sl1, zz + 2.0f + e, b1);
+            lo = fminf(fminf(a0, a1), fminf(c0, c1)) - margin;
+            hi = fmaxf(fmaxf(a0, a1), fmaxf(c0, c1)) + margin;
+          };
+          float lo;
+          window(fz, lo, win_hi);
+          iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
+          // an interval of length L holds at most floor(L) + 1 integers; the
+          // longest window of the wavefront is at one of its ends, which are
+          // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126; every
+          // branch of the column loop is wave-uniform, so all 64 lanes are
+          // active here). The lengths are positive floats, whose bit patterns
+          // order as they do.
+          const float len = win_hi - lo;
+          const int len_a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0);
+          const int len_b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63);
+          nc = (int)(__builtin_bit_cast(float, max(len_a, len_b)) + 1.0e-3f) + 1;
+          if (!zin) iv_lo = n_v;  // reads the column's empty entries only
+        }
+        switch (nc) {
+          case 1:
+          case 2: block_candidates<WF, 2>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 3: block_candidates<WF, 3>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 4: block_candidates<WF, 4>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 5: block_candidates<WF, 5>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 6: block_candidates<WF, 6>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 7: block_candidates<WF, 7>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          case 8: block_candidates<WF, 8>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+          default:
+            // long or unbounded candidate ranges: explicit per-lane loop
+            iv_hi = min(n_v - 1, (int)floorf(fminf(win_hi, (float)n_v)));
+            if (!zin) iv_hi = iv_lo - 1;
+            for (int iv = iv_lo; iv <= iv_hi; ++iv) {
+              const float4 r = R[iv];
+              const uint32_t mr = __float_as_uint(r.x);
+              const int i0 = (int)((mr >> 2) & 0x7fffu);
+              const int i1 = (int)(mr >> 17);
+              float c0, c1;
+              if (p0 >= i0 && p0 < i1) {
+                pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, c0, c1);
+                s00 = __builtin_fmaf(r.w, c0, s00);
+                s01 = __builtin_fmaf(r.w, c1, s01);
+              }
+              if (p0 + 1 >= i0 && p0 + 1 < i1) {
+                pair_weights<WF>(fp1, r.z, r.y, hz, fz, z, c0, c1);
+                s10 = __builtin_fmaf(r.w, c0, s10);
+                s11 = __builtin_fmaf(r.w, c1, s11);
+              }
+            }
+            break;
+        }
+        // block voxel (plane p0 + d, row va + r, z + k) gets wA<d><r> s<d><k>
+        if (m == 0) {
+          acc000 = __builtin_fmaf(wA00, s00, acc000); acc001 = __builtin_fmaf(wA00, s01, acc001);
+          acc010 = __builtin_fmaf(wA01, s00, acc010); acc011 = __builtin_fmaf(wA01, s01, acc011);
+          acc100 = __builtin_fmaf(wA10, s10, acc100); acc101 = __builtin_fmaf(wA10, s11, acc101);
+          acc110 = __builtin_fmaf(wA11, s10, acc110); acc111 = __builtin_fmaf(wA11, s11, acc111);
+        } else {
+          acc000 = __builtin_fmaf(wA00, s00, acc000); acc001 = __builtin_fmaf(wA00, s01, acc001);
+          acc100 = __builtin_fmaf(wA01, s00, acc100); acc101 = __builtin_fmaf(wA01, s01, acc101);
+          acc010 = __builtin_fmaf(wA10, s10, acc010); acc011 = __builtin_fmaf(wA10, s11, acc011);
+          acc110 = __builtin_fmaf(wA11, s10, acc110); acc111 = __builtin_fmaf(wA11, s11, acc111);
+        }
+      }
     }
   }
   if (!zin) return;
@@ -1466,18 +1311,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
   const size_t sx = (size_t)G.n[1] * G.n[2], sy = (size_t)G.n[2];
   float* o = vol + (size_t)x * sx + (size_t)y * sy + z;
   auto put = [&](float* q, float v) { *q = accumulate ? (*q + v) : v; };
-  put(o, acc[0]);
-  if (z1) put(o + 1, acc[1]);
+  put(o, acc000);
+  if (z1) put(o + 1, acc001);
   if (y1) {
-    put(o + sy, acc[2]);
-    if (z1) put(o + sy + 1, acc[3]);
+    put(o + sy, acc010);
+    if (z1) put(o + sy + 1, acc011);
   }
   if (x1) {
-    put(o + sx, acc[4]);
-    if (z1) put(o + sx + 1, acc[5]);
+    put(o + sx, acc100);
+    if (z1) put(o + sx + 1, acc101);
     if (y1) {
-      put(o + sx + sy, acc[6]);
-      if (z1) put(o + sx + sy + 1, acc[7]);
+      put(o + sx + sy, acc110);
+      if (z1) put(o + sx + sy + 1, acc111);
     }
   }
 }
