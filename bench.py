@@ -160,6 +160,8 @@ def cpu_baseline(cfg, G_gjp, vol_np, target_s: float):
 # ---------------------------------------------------------------------------
 def _aux(name, fn, out):
     import torch
+    free, total = torch.cuda.mem_get_info()
+    log(f"{name}: start ({free / 2**30:.1f} of {total / 2**30:.1f} GiB free)")
     t0 = time.perf_counter()
     try:
         out[name] = fn()
@@ -351,6 +353,10 @@ def main():
     ap.add_argument("--only-aux", default="",
                     help="comma list of auxiliary figures to run (adjoint, dtypes, naive, "
                          "batched, t1, c5a, c5b); default all")
+    ap.add_argument("--volume", default="phantom", choices=("phantom", "uniform"),
+                    help="phantom: the workload's ellipsoid phantom (rasterised in FP64); "
+                         "uniform: seeded uniform random values in [0, 1) drawn in FP32 "
+                         "(profiled runs: no double-precision kernels in the process)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy before the steps (untimed), a "
                          "reference dispatch of known traffic for hardware byte counters")
@@ -375,7 +381,11 @@ def main():
     cfg = workloads.config(args.workload)
     log(f"workload {cfg.name}: {cfg.shape} grid, {cfg.n_views} views, {cfg.n_u}x{cfg.n_v}")
     t0 = time.perf_counter()
-    x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    if args.volume == "uniform":
+        x = torch.rand(cfg.shape, generator=torch.Generator(device=dev).manual_seed(11),
+                       device=dev)
+    else:
+        x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
     G = gjp.Geometry.from_config(cfg)
     S = G.count_samples()
     n_rays = cfg.n_rays
@@ -442,11 +452,9 @@ def main():
         vol_np = x.cpu().numpy()
     del x, y
     torch.cuda.empty_cache()
-    if "batched" in want:
-        _aux("batched_c4", lambda: aux_batched(T, torch, gjp, workloads, dev), kernels)
-    if "t1" in want:
-        _aux("t1_table1_geometry", lambda: aux_t1(T, torch, gjp, workloads, dev,
-                                                  not args.no_autotune), kernels)
+    # the largest workloads first, while the device holds nothing else
+    if "c5b" in want:
+        _aux("c5b_2048_f32", lambda: aux_c5b(T, torch, gjp, workloads, dev), kernels)
     if "c5a" in want:
         tiles16 = {}
         for name in ("bf16", "f16"):
@@ -454,8 +462,11 @@ def main():
             if tv:
                 tiles16[name] = (tv, 16 if tv == 128 else 8, 2 if tv == 128 else 4)
         _aux("c5a_1024_16bit", lambda: aux_c5a(T, torch, gjp, workloads, dev, tiles16), kernels)
-    if "c5b" in want:
-        _aux("c5b_2048_f32", lambda: aux_c5b(T, torch, gjp, workloads, dev), kernels)
+    if "t1" in want:
+        _aux("t1_table1_geometry", lambda: aux_t1(T, torch, gjp, workloads, dev,
+                                                  not args.no_autotune), kernels)
+    if "batched" in want:
+        _aux("batched_c4", lambda: aux_batched(T, torch, gjp, workloads, dev), kernels)
 
     out = {
         "metric": METRIC,
@@ -472,7 +483,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{cfg.name}: {cfg.shape[0]}x{cfg.shape[1]}x{cfg.shape[2]} "
-                        f"{'Shepp-Logan-type stand-in' if cfg.phantom == 'sl' else 'random-ellipsoid'} "
+                        f"{'uniform random' if args.volume == 'uniform' else ('Shepp-Logan-type stand-in' if cfg.phantom == 'sl' else 'random-ellipsoid')} "
                         f"volume, {cfg.n_views} {cfg.beam}-beam views, {cfg.n_u}x{cfg.n_v} "
                         f"detector; step = one FP32 forward projection of all views",
             "ray_samples_per_pass": S,

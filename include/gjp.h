@@ -97,7 +97,10 @@ gjp_status gjp_destroy_geometry(gjp_geometry *g);
    overwritten. BF16/FP16 volumes are widened to FP32 in registers; the
    accumulation is FP32 in every case. Two zero-padded pair copies of the
    volume (about 4x its size) are taken from the stream-ordered pool for the
-   duration of the call. The volume must be finite.
+   duration of the call; if the pool cannot serve them, its cached memory is
+   returned to the device (after synchronising `stream`) and the request
+   retried, and failing that they are allocated with hipMalloc and freed
+   after synchronising `stream`. The volume must be finite.
    Errors: GJP_EINVAL (null pointer, unknown dtype), GJP_EUNSUPPORTED (a
    volume plane above about 32 MiB per pair copy, beyond 2048^2 FP32),
    GJP_ENOMEM, GJP_EHIP. */
@@ -144,7 +147,7 @@ gjp_status gjp_forward_project_naive(const gjp_geometry *g, const void *d_vol,
    voxel is written by one thread per launch. d_sino: device,
    n_views*n_u*n_v floats. d_vol: device, n0*n1*n2 floats, overwritten.
    Per-ray tables for a chunk of views are taken from the stream-ordered pool
-   during the call. Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
+   during the call (with the same fallback as gjp_forward_project). Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
 gjp_status gjp_back_project(const gjp_geometry *g, const float *d_sino, float *d_vol,
                             void *stream);
 

@@ -538,11 +538,50 @@ static void keep_pool_memory(int dvc) {
   });
 }
 
+// Blocks that came from hipMalloc because the pool refused them: freed after
+// a stream synchronisation instead of in stream order.
+static std::mutex g_direct_mu;
+static std::set<void*> g_direct;
+
 static hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t s) {
   int dvc = 0;
   (void)hipGetDevice(&dvc);
   keep_pool_memory(dvc);
-  return hipMallocAsync(p, bytes, s);
+  hipError_t e = hipMallocAsync(p, bytes, s);
+  if (e != hipErrorOutOfMemory) return e;
+  // The pool could not serve the block (seen for single blocks of a hundred
+  // GiB and more while the device had room): return its cached memory and
+  // try again, then take the block from the device directly.
+  (void)hipGetLastError();
+  hipMemPool_t pool;
+  if (hipStreamSynchronize(s) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dvc) == hipSuccess)
+    (void)hipMemPoolTrimTo(pool, 0);
+  e = hipMallocAsync(p, bytes, s);
+  if (e == hipSuccess) return e;
+  (void)hipGetLastError();
+  e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
+  }
+  std::lock_guard<std::mutex> lk(g_direct_mu);
+  g_direct.insert(*p);
+  return hipSuccess;
+}
+
+static hipError_t scratch_free(void* p, hipStream_t s) {
+  if (!p) return hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(g_direct_mu);
+    auto it = g_direct.find(p);
+    if (it != g_direct.end()) {
+      g_direct.erase(it);
+      const hipError_t e = hipStreamSynchronize(s);
+      const hipError_t f = hipFree(p);
+      return e != hipSuccess ? e : f;
+    }
+  }
+  return hipFreeAsync(p, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -760,7 +799,7 @@ gjp_status forward_with_tile(const gjp_geometry* g, const void* d_vol, int32_t d
   GJP_HIP(scratch_alloc(&padded, (size_t)(2 * copy_bytes(g->n, dtype)), s),
           "forward: padded pair copies");
   st = forward_into(g, d_views, d_vol, dtype, d_sino, padded, s, tile);
-  const hipError_t fe = hipFreeAsync(padded, s);
+  const hipError_t fe = scratch_free(padded, s);
   if (st != GJP_OK) return (gjp_status)st;
   if (fe != hipSuccess) return hip_fail(fe, "forward: free padded volume");
   return GJP_OK;
@@ -953,8 +992,8 @@ extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sin
   if (e == hipSuccess && g->separable)
     e = scratch_alloc(&cols, (size_t)chunk * g->n_u * col_entry, s);
   if (e != hipSuccess) {
-    (void)hipFreeAsync(table, s);
-    if (mask) (void)hipFreeAsync(mask, s);
+    (void)scratch_free(table, s);
+    (void)scratch_free(mask, s);
     return hip_fail(e, "back_project: scratch");
   }
   for (int v0 = 0; v0 < g->n_views && st == GJP_OK; v0 += (int)chunk) {
@@ -975,9 +1014,9 @@ extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sin
                                       v0 + c0 > 0, d_vol, s);
     }
   }
-  if (cols) (void)hipFreeAsync(cols, s);
-  const hipError_t f1 = hipFreeAsync(table, s);
-  const hipError_t f2 = hipFreeAsync(mask, s);
+  (void)scratch_free(cols, s);
+  const hipError_t f1 = scratch_free(table, s);
+  const hipError_t f2 = scratch_free(mask, s);
   if (st != GJP_OK) return (gjp_status)st;
   if (f1 != hipSuccess) return hip_fail(f1, "back_project: free table");
   if (f2 != hipSuccess) return hip_fail(f2, "back_project: free mask");

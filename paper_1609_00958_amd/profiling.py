@@ -107,8 +107,9 @@ def counter_per_dispatch(pmc_dir: str):
     return vals
 
 
-def scaled_traffic(pmc_dir: str, ref_bytes: float = float(1 << 30)):
-    """Average scaled bytes per dispatch per kernel, and the copy scale factor."""
+def scaled_traffic(pmc_dir: str, ref_bytes: float = float(1 << 30), last: int = 0):
+    """Average scaled bytes per dispatch per kernel (over each kernel's last
+    `last` dispatches if last > 0), and the copy scale factor."""
     vals = counter_per_dispatch(pmc_dir)
     ref = [v for (n, v) in vals.values() if short_name(n) == "copy"]
     if not ref:
@@ -116,10 +117,13 @@ def scaled_traffic(pmc_dir: str, ref_bytes: float = float(1 << 30)):
     ref_kib = max(ref)
     scale = (ref_bytes / 1024.0) / ref_kib
     acc = collections.defaultdict(list)
-    for n, v in vals.values():
+    for d in sorted(vals):
+        n, v = vals[d]
         s = short_name(n)
         if s and s != "copy":
             acc[s].append(v * 1024.0 * scale)
+    if last > 0:
+        acc = {k: v[-last:] for k, v in acc.items()}
     return {k: sum(v) / len(v) for k, v in acc.items()}, scale
 
 
@@ -221,8 +225,8 @@ def main():
     fetch = write = None
     fscale = wscale = None
     if a.fetch and a.write:
-        fetch, fscale = scaled_traffic(a.fetch)
-        write, wscale = scaled_traffic(a.write)
+        fetch, fscale = scaled_traffic(a.fetch, last=a.last)
+        write, wscale = scaled_traffic(a.write, last=a.last)
     head = "launches" if a.last <= 0 else f"launches (last {a.last})"
     lines = [f"# {a.label}", "", "Command(s):", "", "```", a.command, "```", "",
              f"| kernel | {head} | avg ms / launch | HBM fetch GB / launch | "
@@ -235,9 +239,17 @@ def main():
     if fscale:
         lines += ["", f"Byte counters scaled by the 1 GiB copy reference: FETCH_SIZE x {fscale:.3f}, "
                       f"WRITE_SIZE x {wscale:.3f}."]
+    derived = {}
     if a.counters:
+        cstats = counters_last(a.counters, max(a.last, 1))
         lines += ["", "Counters (last " + str(max(a.last, 1)) + " dispatches of each kernel):", ""]
-        lines += counter_table(counters_last(a.counters, max(a.last, 1)))
+        lines += counter_table(cstats)
+        for k, c in cstats.items():
+            for label, fn in DERIVED:
+                try:
+                    derived.setdefault(k, {})[label] = fn(c)
+                except (KeyError, ZeroDivisionError):
+                    pass
     lines += ["", f"Kernel source sha256 (code without comments): `{source_hash()}`", ""]
     with open(a.out_md, "w") as f:
         f.write("\n".join(lines))
@@ -245,7 +257,8 @@ def main():
         data = {"label": a.label, "command": a.command, "source_sha256": source_hash(),
                 "kernels": {k: {"launches": v["calls"], "avg_ms": v["avg_ms"],
                                 "fetch_bytes_per_launch": fetch.get(k) if fetch else None,
-                                "write_bytes_per_launch": write.get(k) if write else None}
+                                "write_bytes_per_launch": write.get(k) if write else None,
+                                "counters": derived.get(k)}
                             for k, v in stats.items()},
                 "copy_scale": {"fetch": fscale, "write": wscale}}
         with open(a.out_json, "w") as f:
