@@ -159,6 +159,8 @@ def forward(vol, geom: Geometry, out=None):
     _check_tensor(out, geom.sino_shape, "sinogram")
     if out.dtype != torch.float32:
         raise TypeError("sinogram must be float32")
+    if out.device != vol.device:
+        raise ValueError("sinogram and volume must be on the same device")
     with torch.cuda.device(vol.device):
         check(lib().gjp_forward_project(geom.handle, vol.data_ptr(), _dtype_code(vol),
                                         out.data_ptr(), _stream(vol.device)))
@@ -191,6 +193,8 @@ def forward_naive(vol, geom: Geometry, out=None):
     _check_tensor(out, geom.sino_shape, "sinogram")
     if out.dtype != torch.float32:
         raise TypeError("sinogram must be float32")
+    if out.device != vol.device:
+        raise ValueError("sinogram and volume must be on the same device")
     with torch.cuda.device(vol.device):
         check(lib().gjp_forward_project_naive(geom.handle, vol.data_ptr(), _dtype_code(vol),
                                               out.data_ptr(), _stream(vol.device)))
@@ -208,6 +212,8 @@ def back(sino, geom: Geometry, out=None):
     _check_tensor(out, geom.shape, "volume")
     if out.dtype != torch.float32:
         raise TypeError("adjoint output must be float32")
+    if out.device != sino.device:
+        raise ValueError("volume and sinogram must be on the same device")
     with torch.cuda.device(sino.device):
         check(lib().gjp_back_project(geom.handle, sino.data_ptr(), out.data_ptr(),
                                      _stream(sino.device)))
