@@ -457,10 +457,9 @@ def main():
         _aux("c5b_2048_f32", lambda: aux_c5b(T, torch, gjp, workloads, dev), kernels)
     if "c5a" in want:
         tiles16 = {}
-        for name in ("bf16", "f16"):
-            tv = kernels.get(f"forward_{name}", {}).get("tile_v")
-            if tv:
-                tiles16[name] = (tv, 16 if tv == 128 else 8, 2 if tv == 128 else 4)
+        for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            if kernels.get(f"forward_{name}", {}).get("tile_v"):
+                tiles16[name] = tuple(gjp.get_forward_tile(G, dt))
         _aux("c5a_1024_16bit", lambda: aux_c5a(T, torch, gjp, workloads, dev, tiles16), kernels)
     if "t1" in want:
         _aux("t1_table1_geometry", lambda: aux_t1(T, torch, gjp, workloads, dev,

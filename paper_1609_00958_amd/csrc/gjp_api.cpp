@@ -634,7 +634,7 @@ bool parse_entry(const std::string& line, std::string& dev, std::string& key, Fw
   std::istringstream in(line);
   int k = 0, vg = 0, rg = 0;
   if (!(in >> dev >> key >> k >> vg >> rg)) return false;
-  if (k < 4 || k > 7 || vg < 1 || vg > 64 || (rg != 2 && rg != 4)) return false;
+  if (k < 4 || k > 8 || vg < 1 || vg > 64 || (rg != 2 && rg != 4)) return false;
   t = FwdTile();
   t.tile_v_log2 = k;
   t.view_group = vg;
@@ -724,9 +724,10 @@ void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* pad
   a.view_group = tile.view_group < 1 ? 1 : tile.view_group;
   a.ru_group = tile.ru_group == 2 ? 2 : 4;
   a.n_views = g->n_views;
-  // k = 7: 128 pixels along v per wavefront row (two per lane), four rows
-  const int tile_v = 1 << tile.tile_v_log2;
-  const int tile_u = tile.tile_v_log2 == 7 ? 4 : 256 >> tile.tile_v_log2;
+  // k = 7: 128 pixels along v per wavefront row (two per lane), four rows;
+  // k = 8: 192 pixels (three per lane), four rows
+  const int tile_v = gjp::tile_v_pixels(tile.tile_v_log2);
+  const int tile_u = tile.tile_v_log2 >= 7 ? 4 : 256 >> tile.tile_v_log2;
   a.tiles_v = (g->n_v + tile_v - 1) / tile_v;
   a.tiles_u = (g->n_u + tile_u - 1) / tile_u;
   a.tiles_per_view = a.tiles_v * a.tiles_u;
@@ -881,10 +882,10 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
   };
   // tile shape and view group with four-plane load groups, then two-plane
   // groups for the best of them
-  // two rays per lane (k = 7) only for 16-bit storage
+  // two or three rays per lane (k = 7, 8) only for 16-bit storage
   const bool pairs = vol_dtype != GJP_F32;
-  for (int k : {7, 6, 5, 4}) {
-    if (k == 7 && !pairs) continue;
+  for (int k : {8, 7, 6, 5, 4}) {
+    if (k >= 7 && !pairs) continue;
     for (int vg : {8, 16, 1}) {
       FwdTile t;
       t.tile_v_log2 = k;
@@ -911,7 +912,7 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
     disk_load(dev);
     disk_store(dev, key, best);
   }
-  if (tile_v_out) *tile_v_out = 1 << best.tile_v_log2;
+  if (tile_v_out) *tile_v_out = gjp::tile_v_pixels(best.tile_v_log2);
   return GJP_OK;
 }
 
@@ -927,13 +928,15 @@ extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dt
     return GJP_OK;
   }
   FwdTile t;
-  if (tile_v == 128 && vol_dtype != GJP_F32) t.tile_v_log2 = 7;
+  if (tile_v == 192 && vol_dtype != GJP_F32) t.tile_v_log2 = 8;
+  else if (tile_v == 128 && vol_dtype != GJP_F32) t.tile_v_log2 = 7;
   else if (tile_v == 64) t.tile_v_log2 = 6;
   else if (tile_v == 32) t.tile_v_log2 = 5;
   else if (tile_v == 16) t.tile_v_log2 = 4;
   else
     return fail(GJP_EINVAL,
-                "gjp_set_forward_tile: tile_v must be 64, 32 or 16 (or 128 for 16-bit storage)");
+                "gjp_set_forward_tile: tile_v must be 64, 32 or 16 (or 128 or 192 for 16-bit "
+                "storage)");
   if (view_group < 1 || view_group > 64)
     return fail(GJP_EINVAL, "gjp_set_forward_tile: view_group must be in [1, 64]");
   if (load_group != 2 && load_group != 4)
@@ -953,7 +956,7 @@ extern "C" gjp_status gjp_get_forward_tile(const gjp_geometry* g, int32_t vol_dt
   if (vol_dtype != GJP_F32 && vol_dtype != GJP_BF16 && vol_dtype != GJP_F16)
     return fail(GJP_EINVAL, "gjp_get_forward_tile: unknown dtype");
   const FwdTile t = tile_for(g, vol_dtype);
-  *tile_v = 1 << t.tile_v_log2;
+  *tile_v = gjp::tile_v_pixels(t.tile_v_log2);
   *view_group = t.view_group;
   *load_group = t.ru_group;
   return GJP_OK;

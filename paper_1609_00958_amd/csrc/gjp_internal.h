@@ -57,7 +57,8 @@ constexpr int kColumnPad = 8;
 
 // Launch configuration of the forward kernel.
 struct FwdTile {
-  int tile_v_log2 = 6;  // detector pixels along v per wavefront row (64, 32, 16)
+  int tile_v_log2 = 6;  // 6, 5, 4: 64, 32, 16 pixels along v per wavefront row;
+                        // 7, 8: 128 / 192 pixels, two / three per lane (16-bit)
   int remap = 1;        // 1: contiguous tile ranges per XCD
   int view_group = 8;   // consecutive views that share each tile's turn
   int ru_group = 4;     // planes whose wide loads a lane issues together (2 or 4)
@@ -123,6 +124,9 @@ int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n
 int batched_grid_size(int cls);
 
 size_t dtype_size(int dtype);
+
+// Detector pixels along v per wavefront row of a forward tile code.
+inline int tile_v_pixels(int tile_v_log2) { return tile_v_log2 == 8 ? 192 : 1 << tile_v_log2; }
 
 // Fixed device scratch of gjp_forward_project_noalloc (gjp_kernels.hip): its
 // size, and its address on the current device (looked up once per device).

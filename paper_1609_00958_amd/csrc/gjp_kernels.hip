@@ -685,14 +685,314 @@ __device__ __forceinline__ void fwd_ray_pair(const FwdArgs& a, int view, int iu,
   }
 }
 
-template <typename T, int WF, bool IDX64, int GRP, bool PAIRS>
+// Four consecutive pair elements at byte offset voff of a 16-bit copy (one
+// 16-byte load): the samples of three rays whose axis-2 floors are z, z or
+// z + 1, and z .. z + 2.
+struct Quadruple {
+  uint32_t e0, e1, e2, e3;
+};
+__device__ __forceinline__ Quadruple buf_quadruple(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+  const u4v v = __builtin_bit_cast(u4v, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+  return {v.x, v.y, v.z, v.w};
+}
+
+// Row interpolation of one pair element: wfa v(a, z) + wca v(a + 1, z), the
+// product issued as a fused w v + (-0) so that FP16 values enter the
+// mixed-precision FMA directly; BF16 values are widened first.
+__device__ __forceinline__ float row_mix(uint32_t e, float wfa, float wca, float nz,
+                                         const f16_t*) {
+  typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+  const h2v h = __builtin_bit_cast(h2v, e);
+  return __builtin_fmaf(wca, (float)h.y, __builtin_fmaf(wfa, (float)h.x, nz));
+}
+__device__ __forceinline__ float row_mix(uint32_t e, float wfa, float wca, float nz,
+                                         const bf16_t*) {
+  return __builtin_fmaf(wca, __uint_as_float(e & 0xffff0000u),
+                        __builtin_fmaf(wfa, __uint_as_float(e << 16), nz));
+}
+
+// Row-uniform loop over three rays per lane (16-bit storage): pixels v, v + 1
+// and v + 2 of one detector column, ordered so that the first has the lowest
+// axis-2 coordinate; the caller has checked that on every plane of [lo, hi)
+// each ray's coordinate exceeds the previous one's by less than one voxel, so
+// the floors are z, z or z + 1, and that or one more. One 16-byte load of the
+// pair elements at z .. z + 3 then serves all three. Each element is first
+// interpolated along the in-plane row (the row and its weights are the same
+// for every ray of the wavefront), then each ray combines the two elements at
+// its floor with its axis-2 weights: the bilinear weights of Eqs. 10-12 in
+// the other order of the two axes, so the sums equal the one-ray loop's up to
+// rounding (not bit for bit).
+constexpr int kTripleGroup = 2;  // planes per load group (three samples each)
+
+template <typename T, int WF, int GRP>
+__device__ __forceinline__ void fwd_loop_rowuniform_triple(const FwdArgs& a, const RaySetup& R1,
+                                                           const RaySetup& R2, const RaySetup& R3,
+                                                           int m, float ca, float ga, int lo, int hi,
+                                                           int mid_lo, int mid_hi, float& acc1,
+                                                           float& acc2, float& acc3) {
+  constexpr uint32_t pe = 2 * sizeof(T);
+  __shared__ float4 s_planes[4][64];
+  float4* slots = s_planes[threadIdx.x >> 6];
+  const char* copy = static_cast<const char*>(m == 0 ? a.vol_a : a.vol_b);
+  const unsigned long long Sm = (unsigned long long)(m == 0 ? a.S0 : a.S1) * pe;
+  const unsigned long long Sa = (unsigned long long)(m == 0 ? a.S1 : a.S0) * pe;
+  const float hia = (m == 0) ? a.G.hi[1] : a.G.hi[0];
+  const float hib = a.G.hi[2];
+  const int lane = (int)(threadIdx.x & 63);
+  const float nz = opaque_neg_zero();
+  acc1 = 0.0f;
+  acc2 = 0.0f;
+  acc3 = 0.0f;
+  for (int base = lo; base < hi; base += 64) {
+    int ia_l;
+    float wfa_l, wca_l;
+    sample_axis<WF>((float)(base + lane), ga, ca, hia, ia_l, wfa_l, wca_l);
+    const int ia_min = __builtin_amdgcn_readfirstlane(wave_min(ia_l));
+    const unsigned long long org = (unsigned long long)(base + 1) * Sm +
+                                   (unsigned long long)(ia_min + 1) * Sa;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(copy + org), (short)0,
+        (int)(uint32_t)min(a.copy_bytes - org, 0xffffffffull), 0x00020000);
+    const uint32_t row_l = (uint32_t)((unsigned long long)lane * Sm +
+                                      (unsigned long long)(ia_l - ia_min) * Sa);
+    slots[lane] = make_float4(__uint_as_float(row_l), wfa_l, wca_l, (float)(base + lane));
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = min(64, hi - base);
+    const int j0 = min(max(mid_lo - base, 0), cnt);
+    const int j1 = min(max(mid_hi - base, j0), cnt);
+    // planes [j0, j1) lie inside all three rays' ranges on every lane
+    auto group = [&](int j, auto check_tag, auto np_tag) {
+      constexpr bool CHECK = decltype(check_tag)::value;
+      constexpr int NP = decltype(np_tag)::value;
+      float4 q[NP];
+      Quadruple u[NP];
+      float wfb1[NP], wcb1[NP], wfb2[NP], wcb2[NP], wfb3[NP], wcb3[NP];
+      bool up2[NP], up3[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) q[k] = slots[j + k];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        // floors compared as floats: only the first ray's becomes an address
+        float f1, f2, f3;
+        sample_axis_floor<WF>(q[k].w, R1.gb, R1.cb, hib, f1, wfb1[k], wcb1[k]);
+        sample_axis_floor<WF>(q[k].w, R2.gb, R2.cb, hib, f2, wfb2[k], wcb2[k]);
+        sample_axis_floor<WF>(q[k].w, R3.gb, R3.cb, hib, f3, wfb3[k], wcb3[k]);
+        up2[k] = f2 != f1;
+        up3[k] = f3 != f2;
+        const uint32_t vo = (uint32_t)((int)f1 + 1) * pe + __float_as_uint(q[k].x);
+        u[k] = buf_quadruple(rs, vo);
+      }
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        if (CHECK) {
+          const int i = base + j + k;
+          const bool in1 = i >= R1.i0 && i < R1.i1, in2 = i >= R2.i0 && i < R2.i1,
+                     in3 = i >= R3.i0 && i < R3.i1;
+          wfb1[k] = in1 ? wfb1[k] : 0.0f;
+          wcb1[k] = in1 ? wcb1[k] : 0.0f;
+          wfb2[k] = in2 ? wfb2[k] : 0.0f;
+          wcb2[k] = in2 ? wcb2[k] : 0.0f;
+          wfb3[k] = in3 ? wfb3[k] : 0.0f;
+          wcb3[k] = in3 ? wcb3[k] : 0.0f;
+        }
+        const float wfa = q[k].y, wca = q[k].z;
+        const float t0 = row_mix(u[k].e0, wfa, wca, nz, (const T*)nullptr);
+        const float t1 = row_mix(u[k].e1, wfa, wca, nz, (const T*)nullptr);
+        const float t2 = row_mix(u[k].e2, wfa, wca, nz, (const T*)nullptr);
+        const float t3 = row_mix(u[k].e3, wfa, wca, nz, (const T*)nullptr);
+        // the second ray's two elements start at its floor: z or z + 1; the
+        // third's one further or not
+        const float p0 = up2[k] ? t1 : t0, p1 = up2[k] ? t2 : t1, p2 = up2[k] ? t3 : t2;
+        const float r0 = up3[k] ? p1 : p0, r1 = up3[k] ? p2 : p1;
+        acc1 = __builtin_fmaf(wcb1[k], t1, __builtin_fmaf(wfb1[k], t0, acc1));
+        acc2 = __builtin_fmaf(wcb2[k], p1, __builtin_fmaf(wfb2[k], p0, acc2));
+        acc3 = __builtin_fmaf(wcb3[k], r1, __builtin_fmaf(wfb3[k], r0, acc3));
+      }
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    using two = std::integral_constant<int, kTripleGroup>;
+    using one = std::integral_constant<int, 1>;
+    int j = 0;
+    for (; j + kTripleGroup <= j0; j += kTripleGroup) group(j, yes(), two());
+    for (; j < j0; ++j) group(j, yes(), one());
+    for (; j + kTripleGroup <= j1; j += kTripleGroup) group(j, no(), two());
+    for (; j < j1; ++j) group(j, no(), one());
+    for (; j + kTripleGroup <= cnt; j += kTripleGroup) group(j, yes(), two());
+    for (; j < cnt; ++j) group(j, yes(), one());
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Is b's axis-2 coordinate above a's by at least eps and at most 1 - eps at
+// the two ends of the plane range (the difference is affine in the plane),
+// or are the two coefficient sets the same?
+__device__ __forceinline__ bool step_ok(float cb_a, float gb_a, float cb_b, float gb_b, float fl,
+                                        float fh, float sign) {
+  if (cb_a == cb_b && gb_a == gb_b) return true;
+  const float al = __builtin_fmaf(fl, gb_a, cb_a), bl = __builtin_fmaf(fl, gb_b, cb_b);
+  const float ah = __builtin_fmaf(fh, gb_a, cb_a), bh = __builtin_fmaf(fh, gb_b, cb_b);
+  const float M = fmaxf(fmaxf(fmaxf(fabsf(al), fabsf(bl)), fmaxf(fabsf(ah), fabsf(bh))), 1.0f);
+  const float eps = M * 0x1p-20f;
+  const float dl = sign * (bl - al), dh = sign * (bh - ah);
+  return dl >= eps && dl <= 1.0f - eps && dh >= eps && dh <= 1.0f - eps;
+}
+
+// Three rays per lane, pixels (iu, iv), (iu, iv + 1) and (iu, iv + 2) of one
+// detector column (16-bit storage). When the wavefront is row-uniform and on
+// every plane each ray's axis-2 coordinate exceeds the previous one's by less
+// than a voxel (checked here, with a margin for single-precision rounding; in
+// either direction along v), one load serves the three rays' samples;
+// otherwise each ray runs the one-ray path.
+template <typename T, int WF, bool IDX64, int GRP>
+__device__ __forceinline__ void fwd_ray_triple(const FwdArgs& a, int view, int iu, int iv,
+                                               bool valid1, bool valid2, bool valid3) {
+  RaySetup R1, R2, R3;
+  const double* vv = a.views + 12 * (size_t)view;
+  {
+    // the first two rays' setups wait in LDS while the next one's double
+    // precision setup runs, so that they are never live in registers
+    // together (the register peak of this kernel)
+    __shared__ float4 s_stash[4][256];
+    RaySetup T1;
+    ray_setup(vv, a.G, iu, iv, T1);
+    s_stash[0][threadIdx.x] = make_float4(T1.ca, T1.ga, T1.cb, T1.gb);
+    s_stash[1][threadIdx.x] = make_float4(__int_as_float(T1.m), __int_as_float(T1.i0),
+                                          __int_as_float(T1.i1), T1.scale);
+    int iv2 = iv + 1;
+    asm volatile("" : "+v"(iv2) : : "memory");
+    RaySetup T2;
+    ray_setup(vv, a.G, iu, iv2, T2);
+    s_stash[2][threadIdx.x] = make_float4(T2.ca, T2.ga, T2.cb, T2.gb);
+    s_stash[3][threadIdx.x] = make_float4(__int_as_float(T2.m), __int_as_float(T2.i0),
+                                          __int_as_float(T2.i1), T2.scale);
+    int iv3 = iv + 2;
+    asm volatile("" : "+v"(iv3) : : "memory");
+    ray_setup(vv, a.G, iu, iv3, R3);
+    asm volatile("" : : "v"(R3.i0), "v"(R3.i1), "v"(R3.cb), "v"(R3.gb), "v"(R3.scale) : "memory");
+    auto unstash = [&](int k, RaySetup& R) {
+      const float4 c0 = s_stash[2 * k][threadIdx.x], c1 = s_stash[2 * k + 1][threadIdx.x];
+      R.ca = c0.x;
+      R.ga = c0.y;
+      R.cb = c0.z;
+      R.gb = c0.w;
+      R.m = __float_as_int(c1.x);
+      R.i0 = __float_as_int(c1.y);
+      R.i1 = __float_as_int(c1.z);
+      R.scale = c1.w;
+      R.ta = R.m == 0 ? 1 : 0;
+      R.tb = R.m == 2 ? 1 : 2;
+    };
+    unstash(0, R1);
+    unstash(1, R2);
+  }
+  if (!valid1) R1.i1 = R1.i0;
+  if (!valid2) R2.i1 = R2.i0;
+  if (!valid3) R3.i1 = R3.i0;
+  const bool has1 = R1.i1 > R1.i0, has2 = R2.i1 > R2.i0, has3 = R3.i1 > R3.i0;
+  // a ray without samples runs a neighbour's coefficients in its place (same
+  // floors, so the shared load is that ray's own) and drops its sum
+  RaySetup P1 = R1, P2 = R2, P3 = R3;
+  if (!has1) {
+    const RaySetup& N = has2 ? R2 : R3;
+    P1.cb = N.cb;
+    P1.gb = N.gb;
+  }
+  if (!has2) {
+    P2.cb = P1.cb;
+    P2.gb = P1.gb;
+  }
+  if (!has3) {
+    P3.cb = P2.cb;
+    P3.gb = P2.gb;
+  }
+  const bool any = has1 || has2 || has3;
+  const uint64_t hv = __ballot(any);
+  bool tripled = false, swap = false;
+  int lm = 2, lo = 0, hi = 0, mid_lo = 0, mid_hi = 0;
+  float lca = 0.0f, lga = 0.0f;
+  if (hv != 0) {
+    const int leader = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)hv) - 1);
+    const RaySetup& L = has1 ? R1 : (has2 ? R2 : R3);
+    lm = __builtin_amdgcn_readlane(L.m, leader);
+    lca = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, L.ca), leader));
+    lga = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, L.ga), leader));
+    const bool off1 = has1 && (R1.m != lm || R1.ca != lca || R1.ga != lga);
+    const bool off2 = has2 && (R2.m != lm || R2.ca != lca || R2.ga != lga);
+    const bool off3 = has3 && (R3.m != lm || R3.ca != lca || R3.ga != lga);
+    if (lm != 2 && __ballot(off1 || off2 || off3) == 0) {
+      const int big = 0x7fffffff;
+      const int i0 = min(min(has1 ? R1.i0 : big, has2 ? R2.i0 : big), has3 ? R3.i0 : big);
+      const int i1 = max(max(has1 ? R1.i1 : -1, has2 ? R2.i1 : -1), has3 ? R3.i1 : -1);
+      const int j0 = max(max(has1 ? R1.i0 : -1, has2 ? R2.i0 : -1), has3 ? R3.i0 : -1);
+      const int j1 = min(min(has1 ? R1.i1 : big, has2 ? R2.i1 : big), has3 ? R3.i1 : big);
+      lo = __builtin_amdgcn_readfirstlane(wave_min(any ? i0 : big));
+      hi = __builtin_amdgcn_readfirstlane(wave_max(any ? i1 : -1));
+      mid_lo = __builtin_amdgcn_readfirstlane(wave_max(any ? j0 : -1));
+      mid_hi = __builtin_amdgcn_readfirstlane(wave_min(any ? j1 : big));
+      const float fl = (float)lo, fh = (float)(hi - 1);
+      const bool pos = step_ok(P1.cb, P1.gb, P2.cb, P2.gb, fl, fh, 1.0f) &&
+                       step_ok(P2.cb, P2.gb, P3.cb, P3.gb, fl, fh, 1.0f);
+      const bool neg = step_ok(P1.cb, P1.gb, P2.cb, P2.gb, fl, fh, -1.0f) &&
+                       step_ok(P2.cb, P2.gb, P3.cb, P3.gb, fl, fh, -1.0f);
+      if (__ballot(!pos) == 0) {
+        tripled = true;
+      } else if (__ballot(!neg) == 0) {
+        tripled = true;
+        swap = true;
+      }
+    }
+  }
+  if (tripled) {
+    // the ray with the lowest axis-2 coordinate addresses the shared load
+    RaySetup A = swap ? P3 : P1, B = P2, C = swap ? P1 : P3;
+    A.i0 = swap ? R3.i0 : R1.i0;
+    A.i1 = swap ? R3.i1 : R1.i1;
+    B.i0 = R2.i0;
+    B.i1 = R2.i1;
+    C.i0 = swap ? R1.i0 : R3.i0;
+    C.i1 = swap ? R1.i1 : R3.i1;
+    float sa, sb, sc;
+    fwd_loop_rowuniform_triple<T, WF, GRP>(a, A, B, C, lm, lca, lga, lo, hi, mid_lo, mid_hi, sa,
+                                           sb, sc);
+    const float acc1 = has1 ? (swap ? sc : sa) : 0.0f;
+    const float acc2 = has2 ? sb : 0.0f;
+    const float acc3 = has3 ? (swap ? sa : sc) : 0.0f;
+    float* out = a.sino + ((size_t)view * a.n_u + iu) * a.n_v + iv;
+    if (valid1) out[0] = acc1 * R1.scale;
+    if (valid2) out[1] = acc2 * R2.scale;
+    if (valid3) out[2] = acc3 * R3.scale;
+  } else {
+    // one ray set after another; the setups are recomputed so that they do
+    // not stay live through the other rays' loops
+    fwd_ray<T, WF, IDX64, GRP>(a, view, iu, iv, valid1);
+    fwd_ray<T, WF, IDX64, GRP>(a, view, iu, iv + 1, valid2);
+    fwd_ray<T, WF, IDX64, GRP>(a, view, iu, iv + 2, valid3);
+  }
+}
+
+// RPL: rays per lane (1; 2 in 128-wide tiles or 3 in 192-wide tiles, 16-bit
+// storage).
+template <typename T, int WF, bool IDX64, int GRP, int RPL>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
   const int tu = t / a.tiles_v;
   const int tv = t - tu * a.tiles_v;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int k = a.tile_v_log2;
-  if constexpr (PAIRS && sizeof(T) == 2) {
+  if constexpr (RPL == 3 && sizeof(T) == 2) {
+    if (k == 8) {
+      // 192 pixels along v per wavefront, three per lane; four columns
+      const int iv = tv * 192 + 3 * lane;
+      const int iu = tu * 4 + wave;
+      const bool col = iu < a.n_u;
+      const bool v1 = col && iv < a.n_v, v2 = v1 && iv + 1 < a.n_v, v3 = v1 && iv + 2 < a.n_v;
+      fwd_ray_triple<T, WF, IDX64, GRP>(a, view, col ? iu : 0, v1 ? iv : 0, v1, v2, v3);
+      return;
+    }
+  }
+  if constexpr (RPL == 2 && sizeof(T) == 2) {
     if (k == 7) {
       // 128 pixels along v per wavefront, two per lane; four columns
       const int iv = (tv << 7) + 2 * lane;
@@ -714,7 +1014,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
 // tile comes up for all the group's views in turn. Rays of nearby views cross
 // nearly the same voxels, so the workgroups resident on an XCD share their
 // volume reads in L2 instead of each view streaming the volume again.
-template <typename T, int WF, bool IDX64, int GRP, bool PAIRS>
+template <typename T, int WF, bool IDX64, int GRP, int RPL>
 __device__ __forceinline__ void fwd_block(const FwdArgs& a) {
   uint32_t b = blockIdx.x;
   if (a.remap) b = xcd_remap(b, gridDim.x);
@@ -724,18 +1024,24 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& a) {
   const uint32_t v0 = grp * K;
   const uint32_t kg = min(K, (uint32_t)a.n_views - v0);  // views in this group
   const uint32_t t = r / kg;
-  fwd_tile<T, WF, IDX64, GRP, PAIRS>(a, (int)(v0 + (r - t * kg)), (int)t);
+  fwd_tile<T, WF, IDX64, GRP, RPL>(a, (int)(v0 + (r - t * kg)), (int)t);
 }
 
 template <typename T, int WF, bool IDX64, int GRP>
 __global__ __launch_bounds__(256) void fwd_kernel(const FwdArgs a) {
-  fwd_block<T, WF, IDX64, GRP, false>(a);
+  fwd_block<T, WF, IDX64, GRP, 1>(a);
 }
 
 // Two rays per lane (16-bit storage, 128-wide tiles).
 template <typename T, int WF, bool IDX64, int GRP>
 __global__ __launch_bounds__(256) void fwd_pair_kernel(const FwdArgs a) {
-  fwd_block<T, WF, IDX64, GRP, true>(a);
+  fwd_block<T, WF, IDX64, GRP, 2>(a);
+}
+
+// Three rays per lane (16-bit storage, 192-wide tiles).
+template <typename T, int WF, bool IDX64, int GRP>
+__global__ __launch_bounds__(256) void fwd_triple_kernel(const FwdArgs a) {
+  fwd_block<T, WF, IDX64, GRP, 3>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1497,48 +1803,39 @@ int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int
   return check_launch("pad kernel");
 }
 
-template <typename T, int WF, bool PAIRS>
-static void launch_fwd_g(const FwdArgs& a, bool idx64, unsigned grid, hipStream_t s) {
-  if constexpr (PAIRS) {
-    if (a.ru_group == 2) {
-      if (idx64)
-        fwd_pair_kernel<T, WF, true, 2><<<grid, 256, 0, s>>>(a);
-      else
-        fwd_pair_kernel<T, WF, false, 2><<<grid, 256, 0, s>>>(a);
-    } else {
-      if (idx64)
-        fwd_pair_kernel<T, WF, true, 4><<<grid, 256, 0, s>>>(a);
-      else
-        fwd_pair_kernel<T, WF, false, 4><<<grid, 256, 0, s>>>(a);
-    }
-  } else {
-    if (a.ru_group == 2) {
-      if (idx64)
-        fwd_kernel<T, WF, true, 2><<<grid, 256, 0, s>>>(a);
-      else
-        fwd_kernel<T, WF, false, 2><<<grid, 256, 0, s>>>(a);
-    } else {
-      if (idx64)
-        fwd_kernel<T, WF, true, 4><<<grid, 256, 0, s>>>(a);
-      else
-        fwd_kernel<T, WF, false, 4><<<grid, 256, 0, s>>>(a);
-    }
-  }
-}
+#define GJP_FWD_LAUNCH(KERNEL)                                   \
+  do {                                                           \
+    if (a.ru_group == 2) {                                       \
+      if (idx64)                                                 \
+        KERNEL<T, WF, true, 2><<<grid, 256, 0, s>>>(a);          \
+      else                                                       \
+        KERNEL<T, WF, false, 2><<<grid, 256, 0, s>>>(a);         \
+    } else {                                                     \
+      if (idx64)                                                 \
+        KERNEL<T, WF, true, 4><<<grid, 256, 0, s>>>(a);          \
+      else                                                       \
+        KERNEL<T, WF, false, 4><<<grid, 256, 0, s>>>(a);         \
+    }                                                            \
+  } while (0)
 
-// Two rays per lane (tile_v_log2 == 7, 16-bit storage only) is a separate
-// kernel: its second ray setup raises the register count, which the one-ray
-// tiles should not pay in occupancy.
+// Two and three rays per lane (tile_v_log2 7 and 8, 16-bit storage only) are
+// kernels of their own: their extra ray setups raise the register count,
+// which the one-ray tiles should not pay in occupancy.
 template <typename T, int WF>
 static void launch_fwd_t(const FwdArgs& a, bool idx64, unsigned grid, hipStream_t s) {
   if constexpr (sizeof(T) == 2) {
+    if (a.tile_v_log2 == 8) {
+      GJP_FWD_LAUNCH(fwd_triple_kernel);
+      return;
+    }
     if (a.tile_v_log2 == 7) {
-      launch_fwd_g<T, WF, true>(a, idx64, grid, s);
+      GJP_FWD_LAUNCH(fwd_pair_kernel);
       return;
     }
   }
-  launch_fwd_g<T, WF, false>(a, idx64, grid, s);
+  GJP_FWD_LAUNCH(fwd_kernel);
 }
+#undef GJP_FWD_LAUNCH
 
 int launch_forward(const FwdArgs& a, int dtype, int weight, bool idx64, int n_views,
                    hipStream_t s) {

@@ -452,6 +452,48 @@ def test_two_rays_per_lane_bitwise(gjp, oracle_mod, case):
     assert_parity(y, oracle_mod.forward(og, rounded), TOL32)
 
 
+# ---------------------------------------------------------------------------
+# three rays per lane (16-bit storage, 192-wide tiles): one 16-byte load serves
+# three rays whose axis-2 coordinates step by less than a voxel; each element
+# is interpolated along the row first, so the sums match the oracle (on the
+# 16-bit-rounded volume) within the FP32 tolerance rather than bit for bit.
+# Geometries where the check fails run the one-ray path.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["cone", "flipped", "coarse", "parallel", "clipped", "spline"])
+def test_three_rays_per_lane(gjp, oracle_mod, case):
+    import torch
+    dev = cuda()
+    shape = (46, 40, 66)
+    n_views, n_u, n_v = 10, 53, 200  # 200 = 192 + 8: a ragged second tile
+    clip = case == "clipped"
+    weight = "spline" if case == "spline" else "linear"
+    if case == "parallel":
+        views = gjp.views_parallel(n_views, 0.9, 0.33, n_u, n_v)
+        beam = "parallel"
+    else:
+        # coarse: v pitch of about 1.7 voxels at the axis, so neighbouring
+        # rays drift more than a voxel apart and the path falls back
+        pv = 2.6 if case == "coarse" else 0.45
+        views = gjp.views_circular_cone(n_views, 160.0, 240.0, 1.2, pv, n_u, n_v)
+        beam = "cone"
+    if case == "flipped":
+        views = _flip_v(views, n_v)
+    G = gjp.Geometry(shape, views, n_u, n_v, beam=beam, clip_cylinder=clip, weight=weight)
+    og = _oracle_geom(oracle_mod, G)
+    vol = workloads.rasterize(workloads.random_ellipsoids(141, shape), shape)
+    vol += np.random.default_rng(142).uniform(0, 0.05, size=shape).astype(np.float32)
+    for dt in (torch.bfloat16, torch.float16):
+        x = _to_dev(vol, dev).to(dt)
+        rounded = x.float().cpu().numpy()
+        want = oracle_mod.forward(og, rounded)
+        for vg, lg in ((16, 2), (1, 4)):
+            gjp.set_forward_tile(G, dt, 192, vg, lg)
+            note(f"three rays per lane {case} {dt}: views {vg} loads {lg}")
+            y = gjp.forward(x, G).cpu().numpy()
+            assert_parity(y, want, TOL32)
+        gjp.reset_forward_tile(G, dt)
+
+
 @pytest.mark.parametrize("beam", ["cone", "parallel"])
 def test_circular_spline_adjoint(gjp, oracle_mod, beam):
     """Spline weights (Eq. 14) on circular trajectories: the column-form gather

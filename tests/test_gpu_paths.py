@@ -266,6 +266,14 @@ def _full_config_check(gjp, oracle_mod, name, n_rays, dtypes=("f32",), pairs=Fal
         want = oracle_mod.forward_rays(og, host, rays)
         note(f"{name}: {dt} parity on {len(rays)} sampled rays")
         assert_parity(got, want, 1e-5)
+        if pairs and dt != "f32":
+            # three rays per lane: row-first interpolation, equal up to rounding
+            note(f"{name}: forward {dt}, three rays per lane")
+            gjp.set_forward_tile(G, tdt, 192, 16, 2)
+            y3 = gjp.forward(xd, G)
+            gjp.set_forward_tile(G, tdt, 64, 8, 4)
+            assert_parity(y3[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy(), want, 1e-5)
+            del y3
         if dt != "f32":
             want32 = oracle_mod.forward_rays(og, x.cpu().numpy(), rays)
             assert_parity(got, want32, 5e-3)
