@@ -202,6 +202,22 @@ def aux_dtypes(T, torch, gjp, G, x, S, fwd_ms, autotune):
     return res
 
 
+def aux_one_ray(T, torch, gjp, G, x, S, fwd_ms):
+    """The FP32 forward with one ray per lane (64-wide tiles: one 16-byte load
+    per sample), then the autotuned configuration again."""
+    y = torch.empty(G.sino_shape, device=x.device)
+    cfg = gjp.get_forward_tile(G, torch.float32)
+    gjp.set_forward_tile(G, torch.float32, 64, 8, 4)
+    try:
+        gjp.forward(x, G, y)
+        r = T.run(lambda: gjp.forward(x, G, y), 3, ("forward",))
+    finally:
+        gjp.set_forward_tile(G, torch.float32, *cfg)
+    ms = r["forward"]["ms_per_launch"]
+    return {"ms": ms, "ray_samples_per_s": S / (ms * 1e-3), "launch_config": [64, 8, 4],
+            "tuned_f32_speedup": ms / fwd_ms}
+
+
 def aux_naive(T, torch, gjp, G, x, S, fwd_ms):
     y = torch.empty(G.sino_shape, device=x.device)
     gjp.forward_naive(x, G, y)
@@ -351,8 +367,8 @@ def main():
     ap.add_argument("--no-aux", action="store_true",
                     help="time the steps only (no auxiliary kernel figures): profiled runs")
     ap.add_argument("--only-aux", default="",
-                    help="comma list of auxiliary figures to run (adjoint, dtypes, naive, "
-                         "batched, t1, c5a, c5b); default all")
+                    help="comma list of auxiliary figures to run (adjoint, dtypes (with the "
+                         "one-ray FP32 forward), naive, batched, t1, c5a, c5b); default all")
     ap.add_argument("--volume", default="phantom", choices=("phantom", "uniform"),
                     help="phantom: the workload's ellipsoid phantom (rasterised in FP64); "
                          "uniform: seeded uniform random values in [0, 1) drawn in FP32 "
@@ -412,16 +428,22 @@ def main():
     log(f"FP32 forward: {step_ms:.2f} ms per step (kernel {fwd_ms:.2f} ms, pad "
         f"{r['pad']['ms_per_launch']:.2f} ms); {value:.4g} ray-samples/s")
 
-    # roofline of the FP32 forward kernel: one irregular 16-byte pair load per
-    # sample and lane is one lane address on the vector-memory address path
-    achieved = S / (fwd_ms * 1e-3)
-    traffic = measured_traffic(cfg.name, "forward_f32")
+    # roofline of the FP32 forward kernel on the vector-memory address path:
+    # each irregular 16-byte load of a lane is one lane address; one per sample
+    # with one ray per lane, two per three samples with three rays per lane
+    # (192-wide tiles, where the rays of a lane share their pair elements)
+    tile_cfg = gjp.get_forward_tile(G, torch.float32)
+    loads_per_sample = 2.0 / 3.0 if tile_cfg[0] == 192 else 1.0
+    fwd_kernel = "forward_f32_triples" if tile_cfg[0] == 192 else "forward_f32"
+    achieved = loads_per_sample * S / (fwd_ms * 1e-3)
+    traffic = measured_traffic(cfg.name, fwd_kernel)
     roofline = {
-        "kernel": "forward_f32",
+        "kernel": fwd_kernel,
         "bound": "vmem_address",
         "achieved": achieved,
         "peak": ADDR_PEAK,
-        "unit": "lane addresses/s (one per ray-sample)",
+        "unit": "lane addresses/s",
+        "lane_addresses_per_sample": loads_per_sample,
         "frac": achieved / ADDR_PEAK,
         "traffic": (traffic[0] + traffic[1]) if traffic else None,
         "hbm_GBps": ((traffic[0] + traffic[1]) / (fwd_ms * 1e-3) / 1e9) if traffic else None,
@@ -430,7 +452,8 @@ def main():
         "access_rate_GBps": (16.0 * S + 4.0 * n_rays) / (fwd_ms * 1e-3) / 1e9,
         "hbm_peak_GBps": HBM_PEAK_GBS,
     }
-    kernels = {"forward_f32": {"ms": fwd_ms, "ray_samples_per_s": achieved, "tile_v": tile,
+    kernels = {"forward_f32": {"ms": fwd_ms, "ray_samples_per_s": S / (fwd_ms * 1e-3),
+                               "tile_v": tile, "launch_config": list(tile_cfg),
                                "pad_ms": r["pad"]["ms_per_launch"]}}
     want = set(a for a in args.only_aux.split(",") if a) or {
         "adjoint", "dtypes", "naive", "batched", "t1", "c5a", "c5b"}
@@ -439,11 +462,18 @@ def main():
     if "adjoint" in want:
         _aux("adjoint", lambda: aux_adjoint(T, torch, gjp, G, x, S, fwd_ms), kernels)
     if "dtypes" in want:
+        _aux("forward_f32_one_ray", lambda: aux_one_ray(T, torch, gjp, G, x, S, fwd_ms), kernels)
+
         def dts():
             d = aux_dtypes(T, torch, gjp, G, x, S, fwd_ms, not args.no_autotune)
             kernels["forward_bf16"], kernels["forward_f16"] = d["bf16"], d["f16"]
-            return {"speedup_bf16_vs_f32": d["bf16"]["speedup_vs_f32"],
-                    "speedup_f16_vs_f32": d["f16"]["speedup_vs_f32"]}
+            out = {"speedup_bf16_vs_f32": d["bf16"]["speedup_vs_f32"],
+                   "speedup_f16_vs_f32": d["f16"]["speedup_vs_f32"]}
+            one = kernels.get("forward_f32_one_ray", {}).get("ms")
+            if one:
+                out["speedup_bf16_vs_f32_one_ray"] = one / d["bf16"]["ms"]
+                out["speedup_f16_vs_f32_one_ray"] = one / d["f16"]["ms"]
+            return out
         _aux("storage_speedups", dts, kernels)
     if "naive" in want:
         _aux("forward_naive_f32", lambda: aux_naive(T, torch, gjp, G, x, S, fwd_ms), kernels)

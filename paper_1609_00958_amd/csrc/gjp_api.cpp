@@ -882,10 +882,10 @@ extern "C" gjp_status gjp_autotune_forward(const gjp_geometry* g, const void* d_
   };
   // tile shape and view group with four-plane load groups, then two-plane
   // groups for the best of them
-  // two or three rays per lane (k = 7, 8) only for 16-bit storage
+  // two rays per lane (k = 7) only for 16-bit storage; three (k = 8) for all
   const bool pairs = vol_dtype != GJP_F32;
   for (int k : {8, 7, 6, 5, 4}) {
-    if (k >= 7 && !pairs) continue;
+    if (k == 7 && !pairs) continue;
     for (int vg : {8, 16, 1}) {
       FwdTile t;
       t.tile_v_log2 = k;
@@ -928,14 +928,14 @@ extern "C" gjp_status gjp_set_forward_tile(const gjp_geometry* g, int32_t vol_dt
     return GJP_OK;
   }
   FwdTile t;
-  if (tile_v == 192 && vol_dtype != GJP_F32) t.tile_v_log2 = 8;
+  if (tile_v == 192) t.tile_v_log2 = 8;
   else if (tile_v == 128 && vol_dtype != GJP_F32) t.tile_v_log2 = 7;
   else if (tile_v == 64) t.tile_v_log2 = 6;
   else if (tile_v == 32) t.tile_v_log2 = 5;
   else if (tile_v == 16) t.tile_v_log2 = 4;
   else
     return fail(GJP_EINVAL,
-                "gjp_set_forward_tile: tile_v must be 64, 32 or 16 (or 128 or 192 for 16-bit "
+                "gjp_set_forward_tile: tile_v must be 192, 64, 32 or 16 (or 128 for 16-bit "
                 "storage)");
   if (view_group < 1 || view_group > 64)
     return fail(GJP_EINVAL, "gjp_set_forward_tile: view_group must be in [1, 64]");

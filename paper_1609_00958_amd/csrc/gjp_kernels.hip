@@ -712,12 +712,13 @@ __device__ __forceinline__ float row_mix(uint32_t e, float wfa, float wca, float
                         __builtin_fmaf(wfa, __uint_as_float(e << 16), nz));
 }
 
-// Row-uniform loop over three rays per lane (16-bit storage): pixels v, v + 1
-// and v + 2 of one detector column, ordered so that the first has the lowest
-// axis-2 coordinate; the caller has checked that on every plane of [lo, hi)
-// each ray's coordinate exceeds the previous one's by less than one voxel, so
-// the floors are z, z or z + 1, and that or one more. One 16-byte load of the
-// pair elements at z .. z + 3 then serves all three. Each element is first
+// Row-uniform loop over three rays per lane: pixels v, v + 1 and v + 2 of one
+// detector column, ordered so that the first has the lowest axis-2
+// coordinate; the caller has checked that on every plane of [lo, hi) each
+// ray's coordinate exceeds the previous one's by less than one voxel, so the
+// floors are z, z or z + 1, and that or one more. The pair elements at
+// z .. z + 3 (one 16-byte load for 16-bit storage, two for FP32) then serve
+// all three. Each element is first
 // interpolated along the in-plane row (the row and its weights are the same
 // for every ray of the wavefront), then each ray combines the two elements at
 // its floor with its axis-2 weights: the bilinear weights of Eqs. 10-12 in
@@ -766,7 +767,8 @@ __device__ __forceinline__ void fwd_loop_rowuniform_triple(const FwdArgs& a, con
       constexpr bool CHECK = decltype(check_tag)::value;
       constexpr int NP = decltype(np_tag)::value;
       float4 q[NP];
-      Quadruple u[NP];
+      Quadruple u[NP];   // 16-bit: four pair elements
+      f4v u0[NP], u1[NP];  // FP32: the same four elements in two loads
       float wfb1[NP], wcb1[NP], wfb2[NP], wcb2[NP], wfb3[NP], wcb3[NP];
       bool up2[NP], up3[NP];
 #pragma unroll
@@ -781,33 +783,46 @@ __device__ __forceinline__ void fwd_loop_rowuniform_triple(const FwdArgs& a, con
         up2[k] = f2 != f1;
         up3[k] = f3 != f2;
         const uint32_t vo = (uint32_t)((int)f1 + 1) * pe + __float_as_uint(q[k].x);
-        u[k] = buf_quadruple(rs, vo);
+        if constexpr (sizeof(T) == 4) {
+          u0[k] = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, 0, 0));
+          u1[k] = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 16u, 0, 0));
+        } else {
+          u[k] = buf_quadruple(rs, vo);
+        }
       }
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
-        if (CHECK) {
-          const int i = base + j + k;
-          const bool in1 = i >= R1.i0 && i < R1.i1, in2 = i >= R2.i0 && i < R2.i1,
-                     in3 = i >= R3.i0 && i < R3.i1;
-          wfb1[k] = in1 ? wfb1[k] : 0.0f;
-          wcb1[k] = in1 ? wcb1[k] : 0.0f;
-          wfb2[k] = in2 ? wfb2[k] : 0.0f;
-          wcb2[k] = in2 ? wcb2[k] : 0.0f;
-          wfb3[k] = in3 ? wfb3[k] : 0.0f;
-          wcb3[k] = in3 ? wcb3[k] : 0.0f;
-        }
         const float wfa = q[k].y, wca = q[k].z;
-        const float t0 = row_mix(u[k].e0, wfa, wca, nz, (const T*)nullptr);
-        const float t1 = row_mix(u[k].e1, wfa, wca, nz, (const T*)nullptr);
-        const float t2 = row_mix(u[k].e2, wfa, wca, nz, (const T*)nullptr);
-        const float t3 = row_mix(u[k].e3, wfa, wca, nz, (const T*)nullptr);
+        float t0, t1, t2, t3;
+        if constexpr (sizeof(T) == 4) {
+          t0 = __builtin_fmaf(wca, u0[k].y, __builtin_fmaf(wfa, u0[k].x, nz));
+          t1 = __builtin_fmaf(wca, u0[k].w, __builtin_fmaf(wfa, u0[k].z, nz));
+          t2 = __builtin_fmaf(wca, u1[k].y, __builtin_fmaf(wfa, u1[k].x, nz));
+          t3 = __builtin_fmaf(wca, u1[k].w, __builtin_fmaf(wfa, u1[k].z, nz));
+        } else {
+          t0 = row_mix(u[k].e0, wfa, wca, nz, (const T*)nullptr);
+          t1 = row_mix(u[k].e1, wfa, wca, nz, (const T*)nullptr);
+          t2 = row_mix(u[k].e2, wfa, wca, nz, (const T*)nullptr);
+          t3 = row_mix(u[k].e3, wfa, wca, nz, (const T*)nullptr);
+        }
         // the second ray's two elements start at its floor: z or z + 1; the
         // third's one further or not
         const float p0 = up2[k] ? t1 : t0, p1 = up2[k] ? t2 : t1, p2 = up2[k] ? t3 : t2;
         const float r0 = up3[k] ? p1 : p0, r1 = up3[k] ? p2 : p1;
-        acc1 = __builtin_fmaf(wcb1[k], t1, __builtin_fmaf(wfb1[k], t0, acc1));
-        acc2 = __builtin_fmaf(wcb2[k], p1, __builtin_fmaf(wfb2[k], p0, acc2));
-        acc3 = __builtin_fmaf(wcb3[k], r1, __builtin_fmaf(wfb3[k], r0, acc3));
+        const float n1 = __builtin_fmaf(wcb1[k], t1, __builtin_fmaf(wfb1[k], t0, acc1));
+        const float n2 = __builtin_fmaf(wcb2[k], p1, __builtin_fmaf(wfb2[k], p0, acc2));
+        const float n3 = __builtin_fmaf(wcb3[k], r1, __builtin_fmaf(wfb3[k], r0, acc3));
+        if (CHECK) {
+          // a ray whose sample range excludes the plane keeps its sum
+          const int i = base + j + k;
+          acc1 = (i >= R1.i0 && i < R1.i1) ? n1 : acc1;
+          acc2 = (i >= R2.i0 && i < R2.i1) ? n2 : acc2;
+          acc3 = (i >= R3.i0 && i < R3.i1) ? n3 : acc3;
+        } else {
+          acc1 = n1;
+          acc2 = n2;
+          acc3 = n3;
+        }
       }
     };
     using yes = std::true_type;
@@ -840,7 +855,7 @@ __device__ __forceinline__ bool step_ok(float cb_a, float gb_a, float cb_b, floa
 }
 
 // Three rays per lane, pixels (iu, iv), (iu, iv + 1) and (iu, iv + 2) of one
-// detector column (16-bit storage). When the wavefront is row-uniform and on
+// detector column. When the wavefront is row-uniform and on
 // every plane each ray's axis-2 coordinate exceeds the previous one's by less
 // than a voxel (checked here, with a margin for single-precision rounding; in
 // either direction along v), one load serves the three rays' samples;
@@ -981,7 +996,7 @@ __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int k = a.tile_v_log2;
-  if constexpr (RPL == 3 && sizeof(T) == 2) {
+  if constexpr (RPL == 3) {
     if (k == 8) {
       // 192 pixels along v per wavefront, three per lane; four columns
       const int iv = tv * 192 + 3 * lane;
@@ -1038,7 +1053,7 @@ __global__ __launch_bounds__(256) void fwd_pair_kernel(const FwdArgs a) {
   fwd_block<T, WF, IDX64, GRP, 2>(a);
 }
 
-// Three rays per lane (16-bit storage, 192-wide tiles).
+// Three rays per lane (192-wide tiles).
 template <typename T, int WF, bool IDX64, int GRP>
 __global__ __launch_bounds__(256) void fwd_triple_kernel(const FwdArgs a) {
   fwd_block<T, WF, IDX64, GRP, 3>(a);
@@ -1818,16 +1833,16 @@ int launch_pad(const void* src, void* copy_a, void* copy_b, int dtype, const int
     }                                                            \
   } while (0)
 
-// Two and three rays per lane (tile_v_log2 7 and 8, 16-bit storage only) are
+// Two rays per lane (tile_v_log2 7, 16-bit storage only) and three (8) are
 // kernels of their own: their extra ray setups raise the register count,
 // which the one-ray tiles should not pay in occupancy.
 template <typename T, int WF>
 static void launch_fwd_t(const FwdArgs& a, bool idx64, unsigned grid, hipStream_t s) {
+  if (a.tile_v_log2 == 8) {
+    GJP_FWD_LAUNCH(fwd_triple_kernel);
+    return;
+  }
   if constexpr (sizeof(T) == 2) {
-    if (a.tile_v_log2 == 8) {
-      GJP_FWD_LAUNCH(fwd_triple_kernel);
-      return;
-    }
     if (a.tile_v_log2 == 7) {
       GJP_FWD_LAUNCH(fwd_pair_kernel);
       return;

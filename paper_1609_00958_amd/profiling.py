@@ -32,6 +32,9 @@ SHORT = (
     ("naive_fwd_kernel<gjp::f16_t", "forward_naive_f16"),
     ("fwd_pair_kernel<gjp::bf16_t", "forward_bf16_pairs"),
     ("fwd_pair_kernel<gjp::f16_t", "forward_f16_pairs"),
+    ("fwd_triple_kernel<float", "forward_f32_triples"),
+    ("fwd_triple_kernel<gjp::bf16_t", "forward_bf16_triples"),
+    ("fwd_triple_kernel<gjp::f16_t", "forward_f16_triples"),
     ("batched_fwd_kernel", "batched"),
     ("batched_pad_kernel", "batched_pad"),
     ("fwd_kernel<float", "forward_f32"),

@@ -453,10 +453,11 @@ def test_two_rays_per_lane_bitwise(gjp, oracle_mod, case):
 
 
 # ---------------------------------------------------------------------------
-# three rays per lane (16-bit storage, 192-wide tiles): one 16-byte load serves
+# three rays per lane (192-wide tiles): one 16-byte load (two for FP32) serves
 # three rays whose axis-2 coordinates step by less than a voxel; each element
 # is interpolated along the row first, so the sums match the oracle (on the
-# 16-bit-rounded volume) within the FP32 tolerance rather than bit for bit.
+# 16-bit-rounded volume for 16-bit storage) within the FP32 tolerance rather
+# than bit for bit.
 # Geometries where the check fails run the one-ray path.
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("case", ["cone", "flipped", "coarse", "parallel", "clipped", "spline"])
@@ -482,7 +483,7 @@ def test_three_rays_per_lane(gjp, oracle_mod, case):
     og = _oracle_geom(oracle_mod, G)
     vol = workloads.rasterize(workloads.random_ellipsoids(141, shape), shape)
     vol += np.random.default_rng(142).uniform(0, 0.05, size=shape).astype(np.float32)
-    for dt in (torch.bfloat16, torch.float16):
+    for dt in (torch.float32, torch.bfloat16, torch.float16):
         x = _to_dev(vol, dev).to(dt)
         rounded = x.float().cpu().numpy()
         want = oracle_mod.forward(og, rounded)
