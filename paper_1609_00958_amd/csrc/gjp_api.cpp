@@ -979,10 +979,15 @@ extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sin
   const float* d_proj = nullptr;
   int st = gjp::geometry_device(g, &d_views, &d_proj);
   if (st != GJP_OK) return (gjp_status)st;
+  // Table layouts: column geometries without clipping take the value table
+  // (4 bytes per ray, positions from each column's affine map), other column
+  // geometries the 16-byte ray table, the rest the 32-byte general table.
+  const bool value = g->separable && !g->gg.clip;
   const size_t per_view =
       (size_t)g->n_u * (size_t)(g->separable ? g->n_v + gjp::kColumnPad : g->n_v);
-  const size_t entry = (g->separable ? 1 : 2) * sizeof(float4);
-  const size_t col_entry = g->separable ? sizeof(float4) : 0;
+  const size_t entry = value ? sizeof(float) : (g->separable ? 1 : 2) * sizeof(float4);
+  const size_t col_entry =
+      value ? sizeof(gjp::ResCol) : (g->separable ? sizeof(float4) : (size_t)0);
   const size_t budget = (size_t)512 << 20;
   long long chunk = (long long)(budget / (per_view * entry + (size_t)g->n_u * col_entry));
   if (chunk < 1) chunk = 1;
@@ -992,29 +997,33 @@ extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sin
   void* cols = nullptr;
   GJP_HIP(scratch_alloc(&table, (size_t)chunk * per_view * entry, s), "back_project: table");
   hipError_t e = scratch_alloc(&mask, (size_t)chunk * sizeof(int), s);
-  if (e == hipSuccess && g->separable)
+  if (e == hipSuccess && col_entry > 0)
     e = scratch_alloc(&cols, (size_t)chunk * g->n_u * col_entry, s);
   if (e != hipSuccess) {
     (void)scratch_free(table, s);
     (void)scratch_free(mask, s);
     return hip_fail(e, "back_project: scratch");
   }
+  float4* t4 = value ? nullptr : static_cast<float4*>(table);
+  float4* c4 = value ? nullptr : static_cast<float4*>(cols);
+  float* tv = value ? static_cast<float*>(table) : nullptr;
+  gjp::ResCol* cv = value ? static_cast<gjp::ResCol*>(cols) : nullptr;
   for (int v0 = 0; v0 < g->n_views && st == GJP_OK; v0 += (int)chunk) {
     const int nc = (int)std::min<long long>(chunk, g->n_views - v0);
     st = gjp::launch_zero_ints(static_cast<int*>(mask), nc, s);
     if (st == GJP_OK)
-      st = gjp::launch_adjoint_table(g, d_views, d_sino, v0, nc, static_cast<float4*>(table),
-                                     static_cast<float4*>(cols), static_cast<int*>(mask), s);
+      st = value ? gjp::launch_adjoint_value_table(g, d_views, d_sino, v0, nc, tv, cv,
+                                                   static_cast<int*>(mask), s)
+                 : gjp::launch_adjoint_table(g, d_views, d_sino, v0, nc, t4, c4,
+                                             static_cast<int*>(mask), s);
     // The gather runs over sub-chunks of views so that all resident
     // workgroups read the same few views' tables (L2-sized working set);
     // each sub-chunk reads and writes the volume once.
     const int sub = g->separable ? kGatherViews : nc;
     for (int c0 = 0; c0 < nc && st == GJP_OK; c0 += sub) {
       const int ns = std::min(sub, nc - c0);
-      st = gjp::launch_adjoint_gather(g, d_proj, static_cast<const float4*>(table),
-                                      static_cast<const float4*>(cols),
-                                      static_cast<const int*>(mask), v0, c0, ns,
-                                      v0 + c0 > 0, d_vol, s);
+      st = gjp::launch_adjoint_gather(g, d_proj, t4, c4, tv, cv, static_cast<const int*>(mask),
+                                      v0, c0, ns, v0 + c0 > 0, d_vol, s);
     }
   }
   (void)scratch_free(cols, s);

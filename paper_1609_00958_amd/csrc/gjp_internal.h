@@ -102,9 +102,25 @@ int launch_forward_naive(const GridGeom& G, const double* views, const void* vol
 int launch_adjoint_table(const gjp_geometry* g, const double* views, const float* sino,
                          int view0, int n_chunk, float4* table, float4* cols, int* mask,
                          hipStream_t s);
+// Column map of the value-table adjoint: every ray v of detector column u
+// has driving axis m, in-plane coordinate fma(i, ga, ca) on plane i and
+// axis-2 coordinate A + v B there, with t = (i - sm) inv_rm, A = a0 + t a1,
+// B = b0 + t b1.
+struct ResCol {
+  int m;  // driving axis (0 or 1); -1: no samples
+  float ca, ga, pad;
+  double sm, inv_rm;
+  double a0, a1, b0, b1;
+};
+int launch_adjoint_value_table(const gjp_geometry* g, const double* views, const float* sino,
+                               int view0, int n_chunk, float* vals, ResCol* cols, int* mask,
+                               hipStream_t s);
+// Column gather from the ray table (table, cols) or, if vals is not null,
+// from the value table (vals, rcols); other geometries: tile splat (table).
 int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
-                          const float4* cols, const int* mask, int view0, int c0, int n_chunk,
-                          bool accumulate, float* vol, hipStream_t s);
+                          const float4* cols, const float* vals, const ResCol* rcols,
+                          const int* mask, int view0, int c0, int n_chunk, bool accumulate,
+                          float* vol, hipStream_t s);
 
 // Batched forward (gjp_batched.cpp / gjp_kernels.hip).
 struct BatchInst {

@@ -1175,6 +1175,79 @@ __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict
   if (b) atomicOr(&mask[cv0 + (int)threadIdx.x], b);
 }
 
+// Value table of the column layout for unclipped column geometries: per ray
+// only y * step length (0 for a ray without samples), each detector column's
+// rays followed by kColumnPad zeros, and per column the double-precision
+// affine map of its rays (ResCol). mask as above.
+__global__ __launch_bounds__(256) void adj_value_table_kernel(const double* __restrict__ views,
+                                                              const GridGeom G,
+                                                              const float* __restrict__ sino,
+                                                              int n_u, int n_v, int view0,
+                                                              long long n_rays,
+                                                              float* __restrict__ vals,
+                                                              ResCol* __restrict__ cols,
+                                                              int* __restrict__ mask) {
+  const long long r = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long per_view = (long long)n_u * n_v;
+  int bits = 0;
+  int cv = 0;
+  if (r < n_rays) {
+    cv = (int)(r / per_view);
+    const long long rem = r - (long long)cv * per_view;
+    const int iu = (int)(rem / n_v);
+    const int iv = (int)(rem - (long long)iu * n_v);
+    const double* v = views + 12 * (size_t)(view0 + cv);
+    RaySetup R;
+    ray_setup(v, G, iu, iv, R);
+    const float y = sino[(size_t)(view0 + cv) * per_view + rem];
+    float* col = vals + ((size_t)cv * n_u + iu) * (size_t)(n_v + kColumnPad);
+    col[iv] = (R.i1 > R.i0) ? y * R.scale : 0.0f;
+    if (iv == 0) {
+      for (int k = 0; k < kColumnPad; ++k) col[n_v + k] = 0.0f;
+      // every ray v of the column: driving axis m, in-plane coordinate
+      // fma(i, ga, ca), axis-2 coordinate A + v B on plane i with
+      // t = (i - sm) inv_rm, A = a0 + t a1, B = b0 + t b1 (dv_m = 0)
+      ResCol c;
+      c.m = R.m < 2 ? R.m : -1;
+      c.ca = R.ca;
+      c.ga = R.ga;
+      c.pad = 0.0f;
+      const int m = c.m < 0 ? 0 : c.m;
+      const double dm = v[3 + m] + (double)iu * v[6 + m];
+      const double d2 = v[5] + (double)iu * v[8];
+      double rm;
+      if (G.beam == BEAM_CONE) {  // s + t (d(v) - s)
+        rm = dm - v[m];
+        c.sm = v[m];
+        c.a0 = v[2];
+        c.a1 = d2 - v[2];
+        c.b0 = 0.0;
+        c.b1 = v[11];
+      } else {  // d(v) + t r
+        rm = v[m];
+        c.sm = dm;
+        c.a0 = d2;
+        c.a1 = v[2];
+        c.b0 = v[11];
+        c.b1 = 0.0;
+      }
+      if (rm == 0.0) c.m = -1;
+      c.inv_rm = rm != 0.0 ? 1.0 / rm : 0.0;
+      cols[(size_t)cv * n_u + iu] = c;
+    }
+    if (R.i1 > R.i0) bits = 1 << R.m;
+  }
+  __shared__ int s_bits[256];
+  s_bits[threadIdx.x] = 0;
+  __syncthreads();
+  const long long r0 = (long long)blockIdx.x * 256;
+  const int cv0 = (int)(r0 / per_view);
+  if (bits) atomicOr(&s_bits[cv - cv0], bits);
+  __syncthreads();
+  const int b = s_bits[threadIdx.x];
+  if (b) atomicOr(&mask[cv0 + (int)threadIdx.x], b);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint pass 2: tile splat. A workgroup owns an ATX x ATY x ATZ voxel tile
 // held in LDS. For every view of the chunk and every driving axis present in
@@ -1430,6 +1503,46 @@ __device__ __forceinline__ void block_candidates(const float4* __restrict__ R, i
   }
 }
 
+// Weights of a sample at signed distance s = p - z from voxel z for the voxels
+// z and z + 1 (the tents of pair_weights on the unclamped coordinate; the
+// spline of Eq. 14 at |s| and |s - 1|).
+template <int WF>
+__device__ __forceinline__ void pair_weights_rel(float s, float& b0, float& b1) {
+  if constexpr (WF == W_LINEAR) {
+    b0 = __builtin_amdgcn_fmed3f(1.0f - __builtin_fabsf(s), 0.0f, 1.0f);
+    b1 = __builtin_amdgcn_fmed3f(s, 2.0f - s, 0.0f);
+  } else {
+    const float t0 = fminf(__builtin_fabsf(s), 1.0f), t1 = fminf(__builtin_fabsf(s - 1.0f), 1.0f);
+    b0 = __builtin_fmaf(t0 * t0, __builtin_fmaf(2.0f, t0, -3.0f), 1.0f);
+    b1 = __builtin_fmaf(t1 * t1, __builtin_fmaf(2.0f, t1, -3.0f), 1.0f);
+  }
+}
+
+// Value-table form of block_candidates (unclipped column geometries): NC
+// candidate values R[iv_lo ...]; candidate k lies at signed distance
+// base_p + k B_p from voxel z on plane p0 + p (base_p formed in double
+// precision per lane, so positions keep single-precision accuracy relative to
+// the voxel).
+template <int WF, int NC>
+__device__ __forceinline__ void block_candidates_val(const float* __restrict__ R, int iv_lo,
+                                                     float base0, float B0, float base1,
+                                                     float B1, float& s00, float& s01,
+                                                     float& s10, float& s11) {
+  float g[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) g[k] = R[iv_lo + k];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    float b0, b1;
+    pair_weights_rel<WF>(__builtin_fmaf((float)k, B0, base0), b0, b1);
+    s00 = __builtin_fmaf(g[k], b0, s00);
+    s01 = __builtin_fmaf(g[k], b1, s01);
+    pair_weights_rel<WF>(__builtin_fmaf((float)k, B1, base1), b0, b1);
+    s10 = __builtin_fmaf(g[k], b0, s10);
+    s11 = __builtin_fmaf(g[k], b1, s11);
+  }
+}
+
 // Workgroup placement of the gather: a lane owns a 2 x 2 x 2 voxel block
 // (x, x+1) x (y, y+1) x (z, z+1); a wavefront covers 128 voxels along axis 2
 // and a workgroup four such wavefronts along y (8 rows). Logical workgroup
@@ -1450,10 +1563,14 @@ __host__ __device__ inline void gather_grid(const int* n, int& nzb, int& nyb, in
 // The two planes of a lane's block along the driving axis m, each with the
 // two in-plane rows: one candidate list per column serves both rows (the
 // column's in-plane weight differs per row, the axis-2 weights do not).
-template <int WF>
+// VAL: value table (adj_value_table_kernel) with positions from each
+// column's affine map and no per-ray range test (unclipped geometries only);
+// otherwise the ray table of adj_table_kernel.
+template <int WF, bool VAL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void adj_gather_sep_kernel(
     const GridGeom G, int n_u, int n_v, const float* __restrict__ proj,
     const float4* __restrict__ rays, const float4* __restrict__ cols,
+    const float* __restrict__ vals, const ResCol* __restrict__ rcols,
     const int* __restrict__ mask, int view0, int c0, int n_chunk, int accumulate,
     float* __restrict__ vol) {
   int nzb, nyb, ntx, nty;
@@ -1473,6 +1590,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
   const int z = 2 * (zb * 64 + (int)(threadIdx.x & 63));
   const bool zin = z < G.n[2];
   const float fz = (float)z;
+  const double dz = (double)z;
   const float hz = G.hi[2];
   const float e = 0.002f;       // widened neighbourhood (voxels)
   const float margin = 0.05f;   // widened ranges (pixels)
@@ -1484,8 +1602,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
     const int mk = mask[c];
     if (!mk) continue;
     const float* P = proj + 12 * (size_t)(view0 + c);
-    const float4* C = cols + (size_t)c * n_u;
-    const float4* RY = rays + (size_t)c * n_u * pitch;
+    const float4* C = VAL ? nullptr : cols + (size_t)c * n_u;
+    const float4* RY = VAL ? nullptr : rays + (size_t)c * n_u * pitch;
+    const ResCol* RC = VAL ? rcols + (size_t)c * n_u : nullptr;
+    const float* RV = VAL ? vals + (size_t)c * n_u * pitch : nullptr;
     for (int m = 0; m < 2; ++m) {
       if (!(mk & (1 << m))) continue;
       const int va = (m == 0) ? y : x;  // first of the two in-plane rows
@@ -1527,7 +1647,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
       const float KA0 = __builtin_fmaf(PfA, fp0, P[7]), KA1 = __builtin_fmaf(PfA, fp1, P[7]);
       const float KW0 = __builtin_fmaf(PfW, fp0, P[11]), KW1 = __builtin_fmaf(PfW, fp1, P[11]);
       for (int iu = iu_lo; iu <= iu_hi; ++iu) {
-        const float4 col = C[iu];
+        float4 col;
+        if constexpr (VAL) {
+          const ResCol& rc = RC[iu];
+          col = make_float4(__int_as_float(rc.m), rc.ca, rc.ga, 0.0f);
+        } else {
+          col = C[iu];
+        }
         if ((int)__float_as_uint(col.x) != m) continue;
         // in-plane weights wA<plane><row> (rows va, va + 1; va is even, as z
         // is, so the tents reproduce the forward's weights exactly)
@@ -1544,7 +1670,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
         const float pa0 = __builtin_fmaf(fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
         const float A0 = __builtin_fmaf(PaA, pa0, KA0), W0 = __builtin_fmaf(PaW, pa0, KW0);
         const float A1 = __builtin_fmaf(PaA, pa1, KA1), W1 = __builtin_fmaf(PaW, pa1, KW1);
-        const float4* R = RY + (size_t)iu * pitch;
+        const float4* R = VAL ? nullptr : RY + (size_t)iu * pitch;
+        const float* RVc = VAL ? RV + (size_t)iu * pitch : nullptr;
         float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
         int nc = 0;  // wave-uniform bound on the candidates per lane
         float win_hi = 3.0e38f;  // upper end of the lane's window (none: every ray)
@@ -1578,37 +1705,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           nc = (int)(__builtin_bit_cast(float, max(len_a, len_b)) + 1.0e-3f) + 1;
           if (!zin) iv_lo = n_v;  // reads the column's empty entries only
         }
-        switch (nc) {
-          case 1:
-          case 2: block_candidates<WF, 2>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 3: block_candidates<WF, 3>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 4: block_candidates<WF, 4>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 5: block_candidates<WF, 5>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 6: block_candidates<WF, 6>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 7: block_candidates<WF, 7>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
-          case 8: block_candidates<WF, 8>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
-          default:
-            // long or unbounded candidate ranges: explicit per-lane loop
-            iv_hi = min(n_v - 1, (int)floorf(fminf(win_hi, (float)n_v)));
-            if (!zin) iv_hi = iv_lo - 1;
-            for (int iv = iv_lo; iv <= iv_hi; ++iv) {
-              const float4 r = R[iv];
-              const uint32_t mr = __float_as_uint(r.x);
-              const int i0 = (int)((mr >> 2) & 0x7fffu);
-              const int i1 = (int)(mr >> 17);
-              float c0, c1;
-              if (p0 >= i0 && p0 < i1) {
-                pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, c0, c1);
-                s00 = __builtin_fmaf(r.w, c0, s00);
-                s01 = __builtin_fmaf(r.w, c1, s01);
+        if constexpr (VAL) {
+          // the column's rays on the two planes: A + v B (double precision)
+          const ResCol& rc = RC[iu];
+          const double t0 = ((double)p0 - rc.sm) * rc.inv_rm;
+          const double t1 = ((double)(p0 + 1) - rc.sm) * rc.inv_rm;
+          const double Ad0 = fma(t0, rc.a1, rc.a0), Bd0 = fma(t0, rc.b1, rc.b0);
+          const double Ad1 = fma(t1, rc.a1, rc.a0), Bd1 = fma(t1, rc.b1, rc.b0);
+          const double dlo = (double)iv_lo;
+          const float base0 = (float)fma(dlo, Bd0, Ad0 - dz);
+          const float base1 = (float)fma(dlo, Bd1, Ad1 - dz);
+          const float B0 = (float)Bd0, B1 = (float)Bd1;
+          switch (nc) {
+            case 1:
+            case 2: block_candidates_val<WF, 2>(RVc, iv_lo, base0, B0, base1, B1, s00, s01, s10, s11); break;
+            case 3: block_candidates_val<WF, 3>(RVc, iv_lo, base0, B0, base1, B1, s00, s01, s10, s11); break;
+            case 4: block_candidates_val<WF, 4>(RVc, iv_lo, base0, B0, base1, B1, s00, s01, s10, s11); break;
+            case 5: block_candidates_val<WF, 5>(RVc, iv_lo, base0, B0, base1, B1, s00, s01, s10, s11); break;
+            case 6: block_candidates_val<WF, 6>(RVc, iv_lo, base0, B0, base1, B1, s00, s01, s10, s11); break;
+            case 7: block_candidates_val<WF, 7>(RVc, iv_lo, base0, B0, base1, B1, s00, s01, s10, s11); break;
+            case 8: block_candidates_val<WF, 8>(RVc, iv_lo, base0, B0, base1, B1, s00, s01, s10, s11); break;
+            default:
+              // long or unbounded candidate ranges: explicit per-lane loop
+              iv_hi = min(n_v - 1, (int)floorf(fminf(win_hi, (float)n_v)));
+              if (!zin) iv_hi = iv_lo - 1;
+              for (int iv = iv_lo; iv <= iv_hi; ++iv) {
+                const float gv = RVc[iv];
+                const float fk = (float)(iv - iv_lo);
+                float c0, c1;
+                pair_weights_rel<WF>(__builtin_fmaf(fk, B0, base0), c0, c1);
+                s00 = __builtin_fmaf(gv, c0, s00);
+                s01 = __builtin_fmaf(gv, c1, s01);
+                pair_weights_rel<WF>(__builtin_fmaf(fk, B1, base1), c0, c1);
+                s10 = __builtin_fmaf(gv, c0, s10);
+                s11 = __builtin_fmaf(gv, c1, s11);
               }
-              if (p0 + 1 >= i0 && p0 + 1 < i1) {
-                pair_weights<WF>(fp1, r.z, r.y, hz, fz, z, c0, c1);
-                s10 = __builtin_fmaf(r.w, c0, s10);
-                s11 = __builtin_fmaf(r.w, c1, s11);
+              break;
+          }
+        } else {
+          switch (nc) {
+            case 1:
+            case 2: block_candidates<WF, 2>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+            case 3: block_candidates<WF, 3>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+            case 4: block_candidates<WF, 4>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+            case 5: block_candidates<WF, 5>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+            case 6: block_candidates<WF, 6>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+            case 7: block_candidates<WF, 7>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+            case 8: block_candidates<WF, 8>(R, iv_lo, p0, fp0, hz, fz, z, s00, s01, s10, s11); break;
+            default:
+              // long or unbounded candidate ranges: explicit per-lane loop
+              iv_hi = min(n_v - 1, (int)floorf(fminf(win_hi, (float)n_v)));
+              if (!zin) iv_hi = iv_lo - 1;
+              for (int iv = iv_lo; iv <= iv_hi; ++iv) {
+                const float4 r = R[iv];
+                const uint32_t mr = __float_as_uint(r.x);
+                const int i0 = (int)((mr >> 2) & 0x7fffu);
+                const int i1 = (int)(mr >> 17);
+                float c0, c1;
+                if (p0 >= i0 && p0 < i1) {
+                  pair_weights<WF>(fp0, r.z, r.y, hz, fz, z, c0, c1);
+                  s00 = __builtin_fmaf(r.w, c0, s00);
+                  s01 = __builtin_fmaf(r.w, c1, s01);
+                }
+                if (p0 + 1 >= i0 && p0 + 1 < i1) {
+                  pair_weights<WF>(fp1, r.z, r.y, hz, fz, z, c0, c1);
+                  s10 = __builtin_fmaf(r.w, c0, s10);
+                  s11 = __builtin_fmaf(r.w, c1, s11);
+                }
               }
-            }
-            break;
+              break;
+          }
         }
         // block voxel (plane p0 + d, row va + r, z + k) gets wA<d><r> s<d><k>
         if (m == 0) {
@@ -1912,9 +2078,23 @@ int launch_adjoint_table(const gjp_geometry* g, const double* views, const float
   return check_launch("adjoint table kernel");
 }
 
+int launch_adjoint_value_table(const gjp_geometry* g, const double* views, const float* sino,
+                               int view0, int n_chunk, float* vals, ResCol* cols, int* mask,
+                               hipStream_t s) {
+  const long long n_rays = (long long)n_chunk * g->n_u * g->n_v;
+  const long long nb = (n_rays + 255) / 256;
+  if (nb > 0xffffffffll) return set_error(-4, "adjoint: view chunk too large");
+  TimedLaunch t = timing_begin("adjoint_table", s);
+  adj_value_table_kernel<<<(unsigned)nb, 256, 0, s>>>(views, g->gg, sino, g->n_u, g->n_v, view0,
+                                                       n_rays, vals, cols, mask);
+  timing_end("adjoint_table", t, s);
+  return check_launch("adjoint table kernel");
+}
+
 int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4* table,
-                          const float4* cols, const int* mask, int view0, int c0, int n_chunk,
-                          bool accumulate, float* vol, hipStream_t s) {
+                          const float4* cols, const float* vals, const ResCol* rcols,
+                          const int* mask, int view0, int c0, int n_chunk, bool accumulate,
+                          float* vol, hipStream_t s) {
   TimedLaunch t = timing_begin("adjoint_gather", s);
   const int acc = accumulate ? 1 : 0;
   if (g->separable) {
@@ -1923,14 +2103,22 @@ int launch_adjoint_gather(const gjp_geometry* g, const float* proj, const float4
     const unsigned long long nwg = (unsigned long long)ntx * GTX * nty * GTY * nzb;
     if (nwg > 0x7fffffffull) return set_error(-4, "adjoint: volume too large for one launch");
     const unsigned grid = (unsigned)nwg;
-    if (g->weight == W_SPLINE)
-      adj_gather_sep_kernel<W_SPLINE><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table,
-                                                           cols, mask, view0, c0, n_chunk, acc,
-                                                           vol);
-    else
-      adj_gather_sep_kernel<W_LINEAR><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table,
-                                                           cols, mask, view0, c0, n_chunk, acc,
-                                                           vol);
+#define GJP_GATHER(W, V)                                                                      \
+  adj_gather_sep_kernel<W, V><<<grid, 256, 0, s>>>(g->gg, g->n_u, g->n_v, proj, table, cols, \
+                                                   vals, rcols, mask, view0, c0, n_chunk, acc, \
+                                                   vol)
+    if (vals) {
+      if (g->weight == W_SPLINE)
+        GJP_GATHER(W_SPLINE, true);
+      else
+        GJP_GATHER(W_LINEAR, true);
+    } else {
+      if (g->weight == W_SPLINE)
+        GJP_GATHER(W_SPLINE, false);
+      else
+        GJP_GATHER(W_LINEAR, false);
+    }
+#undef GJP_GATHER
   } else {
     if (c0 != 0) return set_error(-4, "adjoint: the tile splat takes whole chunks");
     dim3 grid((unsigned)((g->n[2] + ATZ - 1) / ATZ), (unsigned)((g->n[1] + ATY - 1) / ATY),

@@ -34,8 +34,13 @@ int launch_forward_naive(const GridGeom&, const double*, const void*, int, int, 
 int launch_adjoint_table(const gjp_geometry*, const double*, const float*, int, int, float4*,
                          float4*, int*, hipStream_t) { return stub("table"); }
 int launch_adjoint_gather(const gjp_geometry*, const float*, const float4*, const float4*,
-                          const int*, int, int, int, bool, float*, hipStream_t) {
+                          const float*, const ResCol*, const int*, int, int, int, bool, float*,
+                          hipStream_t) {
   return stub("gather");
+}
+int launch_adjoint_value_table(const gjp_geometry*, const double*, const float*, int, int, float*,
+                               ResCol*, int*, hipStream_t) {
+  return stub("value table");
 }
 int launch_batched_pad(const BatchInst*, int, hipStream_t) { return stub("batched pad"); }
 int launch_batched_forward(const BatchInst*, const uint2*, int, int*, int, int, hipStream_t) {
