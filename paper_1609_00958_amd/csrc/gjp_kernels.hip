@@ -1665,53 +1665,78 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           wA11 = 0.0f;
         }
         if (wA00 == 0.0f && wA01 == 0.0f && wA10 == 0.0f && wA11 == 0.0f) continue;
-        // v of the column's rays on each plane: (A + P6 z) / W, affine in z;
-        // A and W are the plane terms (per axis) plus the column's in-plane term
-        const float pa0 = __builtin_fmaf(fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
-        const float A0 = __builtin_fmaf(PaA, pa0, KA0), W0 = __builtin_fmaf(PaW, pa0, KW0);
-        const float A1 = __builtin_fmaf(PaA, pa1, KA1), W1 = __builtin_fmaf(PaW, pa1, KW1);
         const float4* R = VAL ? nullptr : RY + (size_t)iu * pitch;
         const float* RVc = VAL ? RV + (size_t)iu * pitch : nullptr;
         float s00 = 0.0f, s01 = 0.0f, s10 = 0.0f, s11 = 0.0f;
         int nc = 0;  // wave-uniform bound on the candidates per lane
         float win_hi = 3.0e38f;  // upper end of the lane's window (none: every ray)
         int iv_lo = 0, iv_hi = n_v - 1;
-        if (W0 > 1.0e-6f && W1 > 1.0e-6f) {
-          // rays whose axis-2 coordinate lies in [z - 1, z + 2) on either plane
-          const float inv0 = __builtin_amdgcn_rcpf(W0), inv1 = __builtin_amdgcn_rcpf(W1);
-          const float sl0 = P[6] * inv0, sl1 = P[6] * inv1;  // pixels per voxel along z
-          const float b0 = A0 * inv0, b1 = A1 * inv1;
-          // span of the union window at axis-2 position zz (convex in zz)
-          auto window = [&](float zz, float& lo, float& hi) {
-            const float a0 = __builtin_fmaf(sl0, zz - 1.0f - e, b0);
-            const float a1 = __builtin_fmaf(sl0, zz + 2.0f + e, b0);
-            const float c0 = __builtin_fmaf(sl1, zz - 1.0f - e, b1);
-            const float c1 = __builtin_fmaf(sl1, zz + 2.0f + e, b1);
-            lo = fminf(fminf(a0, a1), fminf(c0, c1)) - margin;
-            hi = fmaxf(fmaxf(a0, a1), fmaxf(c0, c1)) + margin;
-          };
-          float lo;
-          window(fz, lo, win_hi);
-          iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
-          // an interval of length L holds at most floor(L) + 1 integers; the
-          // longest window of the wavefront is at one of its ends, which are
-          // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126; every
-          // branch of the column loop is wave-uniform, so all 64 lanes are
-          // active here). The lengths are positive floats, whose bit patterns
-          // order as they do.
-          const float len = win_hi - lo;
-          const int len_a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0);
-          const int len_b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63);
-          nc = (int)(__builtin_bit_cast(float, max(len_a, len_b)) + 1.0e-3f) + 1;
-          if (!zin) iv_lo = n_v;  // reads the column's empty entries only
-        }
+        double Ad0 = 0.0, Bd0 = 0.0, Ad1 = 0.0, Bd1 = 0.0;
         if constexpr (VAL) {
-          // the column's rays on the two planes: A + v B (double precision)
+          // the column's rays on the two planes: A + v B (double precision);
+          // ray v reaches axis-2 position zz at v = (zz - A) / B
           const ResCol& rc = RC[iu];
           const double t0 = ((double)p0 - rc.sm) * rc.inv_rm;
-          const double t1 = ((double)(p0 + 1) - rc.sm) * rc.inv_rm;
-          const double Ad0 = fma(t0, rc.a1, rc.a0), Bd0 = fma(t0, rc.b1, rc.b0);
-          const double Ad1 = fma(t1, rc.a1, rc.a0), Bd1 = fma(t1, rc.b1, rc.b0);
+          Ad0 = fma(t0, rc.a1, rc.a0);
+          Bd0 = fma(t0, rc.b1, rc.b0);
+          Ad1 = fma(rc.inv_rm, rc.a1, Ad0);
+          Bd1 = fma(rc.inv_rm, rc.b1, Bd0);
+          const float Bf0 = (float)Bd0, Bf1 = (float)Bd1;
+          const float ib0 = __builtin_amdgcn_rcpf(Bf0), ib1 = __builtin_amdgcn_rcpf(Bf1);
+          if (Bf0 * Bf1 > 0.0f && __builtin_fabsf(ib0) < 1.0e4f && __builtin_fabsf(ib1) < 1.0e4f) {
+            // rays whose axis-2 coordinate lies in [z - 1, z + 2) on either plane
+            const float Af0 = (float)Ad0, Af1 = (float)Ad1;
+            const float za = fz - 1.0f - e, zc = fz + 2.0f + e;
+            const float a0 = (za - Af0) * ib0, a1 = (zc - Af0) * ib0;
+            const float c0 = (za - Af1) * ib1, c1 = (zc - Af1) * ib1;
+            const float lo = fminf(fminf(a0, a1), fminf(c0, c1)) - 0.01f;
+            win_hi = fmaxf(fmaxf(a0, a1), fmaxf(c0, c1)) + 0.01f;
+            iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
+            // longest window of the wavefront: lanes 0 and 63, as below
+            const float len = win_hi - lo;
+            const int len_a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0);
+            const int len_b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63);
+            nc = (int)(__builtin_bit_cast(float, max(len_a, len_b)) + 1.0e-3f) + 1;
+            if (!zin) iv_lo = n_v;  // reads the column's zero padding only
+          }
+        } else {
+          // v of the column's rays on each plane: (A + P6 z) / W, affine in z;
+          // A and W are the plane terms (per axis) plus the column's in-plane term
+          const float pa0 = __builtin_fmaf(fp0, col.z, col.y), pa1 = __builtin_fmaf(fp1, col.z, col.y);
+          const float A0 = __builtin_fmaf(PaA, pa0, KA0), W0 = __builtin_fmaf(PaW, pa0, KW0);
+          const float A1 = __builtin_fmaf(PaA, pa1, KA1), W1 = __builtin_fmaf(PaW, pa1, KW1);
+          if (W0 > 1.0e-6f && W1 > 1.0e-6f) {
+            // rays whose axis-2 coordinate lies in [z - 1, z + 2) on either plane
+            const float inv0 = __builtin_amdgcn_rcpf(W0), inv1 = __builtin_amdgcn_rcpf(W1);
+            const float sl0 = P[6] * inv0, sl1 = P[6] * inv1;  // pixels per voxel along z
+            const float b0 = A0 * inv0, b1 = A1 * inv1;
+            // span of the union window at axis-2 position zz (convex in zz)
+            auto window = [&](float zz, float& lo, float& hi) {
+              const float a0 = __builtin_fmaf(sl0, zz - 1.0f - e, b0);
+              const float a1 = __builtin_fmaf(sl0, zz + 2.0f + e, b0);
+              const float c0 = __builtin_fmaf(sl1, zz - 1.0f - e, b1);
+              const float c1 = __builtin_fmaf(sl1, zz + 2.0f + e, b1);
+              lo = fminf(fminf(a0, a1), fminf(c0, c1)) - margin;
+              hi = fmaxf(fmaxf(a0, a1), fmaxf(c0, c1)) + margin;
+            };
+            float lo;
+            window(fz, lo, win_hi);
+            iv_lo = min(max((int)ceilf(fmaxf(lo, -1.0f)), 0), n_v);
+            // an interval of length L holds at most floor(L) + 1 integers; the
+            // longest window of the wavefront is at one of its ends, which are
+            // lanes 0 and 63 (axis-2 positions 128 zb and 128 zb + 126; every
+            // branch of the column loop is wave-uniform, so all 64 lanes are
+            // active here). The lengths are positive floats, whose bit patterns
+            // order as they do.
+            const float len = win_hi - lo;
+            const int len_a = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 0);
+            const int len_b = __builtin_amdgcn_readlane(__builtin_bit_cast(int, len), 63);
+            nc = (int)(__builtin_bit_cast(float, max(len_a, len_b)) + 1.0e-3f) + 1;
+            if (!zin) iv_lo = n_v;  // reads the column's empty entries only
+          }
+        }
+        if constexpr (VAL) {
+          // candidate positions relative to the voxel, from iv_lo on
           const double dlo = (double)iv_lo;
           const float base0 = (float)fma(dlo, Bd0, Ad0 - dz);
           const float base1 = (float)fma(dlo, Bd1, Ad1 - dz);

@@ -40,8 +40,7 @@ SHORT = (
     ("fwd_kernel<float", "forward_f32"),
     ("fwd_kernel<gjp::bf16_t", "forward_bf16"),
     ("fwd_kernel<gjp::f16_t", "forward_f16"),
-    ("adj_resample_kernel", "adjoint_resample"),
-    ("res_table_kernel", "adjoint_resample_table"),
+    ("adj_value_table_kernel", "adjoint_table"),
     ("adj_gather_sep_kernel", "adjoint_gather"),
     ("adj_splat_kernel", "adjoint_gather"),
     ("adj_table_kernel", "adjoint_table"),
