@@ -1176,9 +1176,11 @@ __global__ __launch_bounds__(256) void adj_table_kernel(const double* __restrict
 }
 
 // Value table of the column layout for unclipped column geometries: per ray
-// only y * step length (0 for a ray without samples), each detector column's
-// rays followed by kColumnPad zeros, and per column the double-precision
-// affine map of its rays (ResCol). mask as above.
+// only y * step length, each detector column's rays followed by kColumnPad
+// zeros, and per column the double-precision affine map of its rays
+// (ResCol). Only the ray's line is set up (no sample range: without clipping
+// a ray with no samples has no position within a voxel of the grid, so the
+// gather never weights its value). mask: driving axes per view.
 __global__ __launch_bounds__(256) void adj_value_table_kernel(const double* __restrict__ views,
                                                               const GridGeom G,
                                                               const float* __restrict__ sino,
@@ -1197,34 +1199,38 @@ __global__ __launch_bounds__(256) void adj_value_table_kernel(const double* __re
     const int iu = (int)(rem / n_v);
     const int iv = (int)(rem - (long long)iu * n_v);
     const double* v = views + 12 * (size_t)(view0 + cv);
-    RaySetup R;
-    ray_setup(v, G, iu, iv, R);
+    double s[3], g[3];
+    int m, a, b;
+    float scale;
+    const bool dir = ray_line(v, G, iu, iv, s, g, m, a, b, scale);
     const float y = sino[(size_t)(view0 + cv) * per_view + rem];
     float* col = vals + ((size_t)cv * n_u + iu) * (size_t)(n_v + kColumnPad);
-    col[iv] = (R.i1 > R.i0) ? y * R.scale : 0.0f;
+    col[iv] = y * scale;
     if (iv == 0) {
       for (int k = 0; k < kColumnPad; ++k) col[n_v + k] = 0.0f;
       // every ray v of the column: driving axis m, in-plane coordinate
-      // fma(i, ga, ca), axis-2 coordinate A + v B on plane i with
-      // t = (i - sm) inv_rm, A = a0 + t a1, B = b0 + t b1 (dv_m = 0)
+      // fma(i, ga, ca) (the forward's coefficients), axis-2 coordinate
+      // A + v B on plane i with t = (i - sm) inv_rm, A = a0 + t a1,
+      // B = b0 + t b1 (dv_m = 0)
       ResCol c;
-      c.m = R.m < 2 ? R.m : -1;
-      c.ca = R.ca;
-      c.ga = R.ga;
+      c.m = (dir && m < 2) ? m : -1;
+      const double neg_sm = -s[m];
+      c.ca = dir ? (float)(s[a] + neg_sm * g[a]) : 0.0f;
+      c.ga = dir ? (float)g[a] : 0.0f;
       c.pad = 0.0f;
-      const int m = c.m < 0 ? 0 : c.m;
-      const double dm = v[3 + m] + (double)iu * v[6 + m];
+      const int mm = c.m < 0 ? 0 : c.m;
+      const double dm = v[3 + mm] + (double)iu * v[6 + mm];
       const double d2 = v[5] + (double)iu * v[8];
       double rm;
       if (G.beam == BEAM_CONE) {  // s + t (d(v) - s)
-        rm = dm - v[m];
-        c.sm = v[m];
+        rm = dm - v[mm];
+        c.sm = v[mm];
         c.a0 = v[2];
         c.a1 = d2 - v[2];
         c.b0 = 0.0;
         c.b1 = v[11];
       } else {  // d(v) + t r
-        rm = v[m];
+        rm = v[mm];
         c.sm = dm;
         c.a0 = d2;
         c.a1 = v[2];
@@ -1234,8 +1240,8 @@ __global__ __launch_bounds__(256) void adj_value_table_kernel(const double* __re
       if (rm == 0.0) c.m = -1;
       c.inv_rm = rm != 0.0 ? 1.0 / rm : 0.0;
       cols[(size_t)cv * n_u + iu] = c;
+      if (c.m >= 0) bits = 1 << c.m;
     }
-    if (R.i1 > R.i0) bits = 1 << R.m;
   }
   __shared__ int s_bits[256];
   s_bits[threadIdx.x] = 0;
@@ -1244,8 +1250,8 @@ __global__ __launch_bounds__(256) void adj_value_table_kernel(const double* __re
   const int cv0 = (int)(r0 / per_view);
   if (bits) atomicOr(&s_bits[cv - cv0], bits);
   __syncthreads();
-  const int b = s_bits[threadIdx.x];
-  if (b) atomicOr(&mask[cv0 + (int)threadIdx.x], b);
+  const int bo = s_bits[threadIdx.x];
+  if (bo) atomicOr(&mask[cv0 + (int)threadIdx.x], bo);
 }
 
 // ---------------------------------------------------------------------------

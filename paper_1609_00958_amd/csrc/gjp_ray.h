@@ -83,12 +83,14 @@ GJP_HD void axis_interval(double s_k, double s_m, double g_k, int n_k, double& l
   hi = t0 < t1 ? t1 : t0;
 }
 
-// Per-ray setup for pixel (iu, iv) of a view given in grid units:
-// v[0..2] = source (cone) or direction (parallel), v[3..5] = det00,
-// v[6..8] = du, v[9..11] = dv.
-GJP_HD void ray_setup(const double* __restrict__ v, const GridGeom& G, int iu, int iv,
-                      RaySetup& R) {
-  double d[3], s[3], r[3];
+// The line of pixel (iu, iv) of a view given in grid units (v[0..2] = source
+// (cone) or direction (parallel), v[3..5] = det00, v[6..8] = du,
+// v[9..11] = dv): origin s (Eq. 2), driving axis m (Eq. 3, ties to the lowest
+// axis), transverse axes a < b, slopes g = r / r_m (Eq. 4) and the
+// world-space length of one plane step. False for a ray without direction.
+GJP_HD bool ray_line(const double* __restrict__ v, const GridGeom& G, int iu, int iv, double* s,
+                     double* g, int& m, int& a, int& b, float& scale) {
+  double d[3], r[3];
   for (int k = 0; k < 3; ++k) d[k] = v[3 + k] + (double)iu * v[6 + k] + (double)iv * v[9 + k];
   if (G.beam == BEAM_CONE) {
     for (int k = 0; k < 3; ++k) {
@@ -101,27 +103,38 @@ GJP_HD void ray_setup(const double* __restrict__ v, const GridGeom& G, int iu, i
       r[k] = v[k];
     }
   }
-  // Eq. 3, ties to the lowest axis
-  int m = 0;
+  m = 0;
   if (fabs(r[1]) > fabs(r[m])) m = 1;
   if (fabs(r[2]) > fabs(r[m])) m = 2;
-  const int a = (m == 0) ? 1 : 0;
-  const int b = (m == 2) ? 1 : 2;
+  a = (m == 0) ? 1 : 0;
+  b = (m == 2) ? 1 : 2;
+  scale = 0.0f;
+  if (r[m] == 0.0) return false;
+  g[a] = r[a] / r[m];
+  g[b] = r[b] / r[m];
+  g[m] = 1.0;
+  double q = 0.0;
+  for (int k = 0; k < 3; ++k) q += (g[k] * G.vs[k]) * (g[k] * G.vs[k]);
+  scale = (float)sqrt(q);
+  return true;
+}
+
+// Per-ray setup for pixel (iu, iv): the line above, single-precision
+// coefficients of the transverse coordinates and the exact sample range.
+GJP_HD void ray_setup(const double* __restrict__ v, const GridGeom& G, int iu, int iv,
+                      RaySetup& R) {
+  double s[3], g[3];
+  int m, a, b;
+  float scale;
+  const bool dir = ray_line(v, G, iu, iv, s, g, m, a, b, scale);
   R.m = m;
   R.ta = a;
   R.tb = b;
   R.i0 = 0;
   R.i1 = 0;
   R.ca = R.ga = R.cb = R.gb = 0.0f;
-  R.scale = 0.0f;
-  if (r[m] == 0.0) return;  // no direction: no samples
-  double g[3];
-  g[a] = r[a] / r[m];  // Eq. 4
-  g[b] = r[b] / r[m];
-  g[m] = 1.0;
-  double q = 0.0;
-  for (int k = 0; k < 3; ++k) q += (g[k] * G.vs[k]) * (g[k] * G.vs[k]);
-  R.scale = (float)sqrt(q);
+  R.scale = scale;
+  if (!dir) return;  // no direction: no samples
   const double neg_sm = -s[m];  // Eq. 5
   R.ca = (float)(s[a] + neg_sm * g[a]);
   R.ga = (float)g[a];
