@@ -12,9 +12,10 @@ autotuned before the untimed warm-up.
 The same run then times, each after its own warm-up, and reports under
 `kernels`: the FP32 adjoint A^T y (table and gather passes), BF16 and FP16
 storage forwards and their speed-up over FP32, the plain one-lane-per-ray FP32
-forward, one batched launch of the 32-instance uneven workload, the paper's
-speed geometry (Table I: ms per projection), a 1024^3 BF16/FP16 forward and a
-2048^3 FP32 forward. `roofline` refers to the FP32 forward kernel and its
+forward, 20 gradient-descent steps of the differentiable projector, one
+batched launch of the 32-instance uneven workload, the paper's speed geometry
+(Table I: ms per projection), a 1024^3 BF16/FP16 forward, a 2048^3 FP32
+forward and SART iterations on the 256^3 workload. `roofline` refers to the FP32 forward kernel and its
 binding unit (the vector-memory address path); the HBM fraction from the
 committed byte counters and the paper's access rate are reported beside it.
 
@@ -298,6 +299,65 @@ def aux_c5b(T, torch, gjp, workloads, dev):
             "ray_samples_per_s": S / (ms * 1e-3)}
 
 
+def aux_gd(T, torch, gjp, G, x_true, steps=20):
+    """The differentiable-projector run of the 512^3 workload: loss
+    0.5 ||Ax - b||^2 through the autograd wrapper (forward A, backward the
+    hand-written A^T), `steps` gradient-descent steps from x = 0 with step
+    1/lambda (lambda from three power iterations on A^T A, untimed). b is the
+    forward projection of the phantom plus seeded Gaussian noise (sigma = 1% of
+    max b): the steps' cost does not depend on b's values."""
+    b = gjp.forward(x_true, G)
+    gen = torch.Generator(device="cpu").manual_seed(3)
+    b = b + (0.01 * float(b.max())) * torch.randn(G.sino_shape, generator=gen).to(b.device)
+    q = torch.rand(G.shape, generator=torch.Generator().manual_seed(32)).to(b.device)
+    lam = 1.0
+    for _ in range(3):
+        q = gjp.back(gjp.forward(q, G), G)
+        lam = float(torch.linalg.vector_norm(q))
+        q = q / lam
+    del q
+    x = torch.zeros(G.shape, device=b.device, requires_grad=True)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.grad = None
+        r = gjp.project(x, G) - b
+        L = 0.5 * (r * r).sum()
+        L.backward()
+        losses.append(L.detach())
+        with torch.no_grad():
+            x -= x.grad / lam
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    losses = [float(v) for v in losses]
+    return {"workload": "c3 differentiable projector: 512^3, 720 views, 768^2; loss "
+                        "0.5||Ax - b||^2, gradient through the hand-written adjoint",
+            "steps": steps, "s_total": dt, "ms_per_step": 1e3 * dt / steps,
+            "loss_first_last": [losses[0], losses[-1]],
+            "loss_monotone": all(l2 < l1 for l1, l2 in zip(losses, losses[1:]))}
+
+
+def aux_sart(torch, gjp, workloads, dev, iters=3):
+    """SART (Sec. IV-B) on the 256^3 / 360-view workload: 20 ordered subsets
+    of 18 views; one iteration = every subset updated once."""
+    cfg = workloads.config("c2")
+    x_true = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
+    G = gjp.Geometry.from_config(cfg)
+    S = G.count_samples()
+    b = gjp.forward(x_true, G)
+    solver = gjp.SART(G, 20, lam=1.0)
+    x = solver.run(b, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = solver.run(b, iters, x0=x)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / iters
+    return {"workload": "sart: 256^3 random-ellipsoid volume, 360 cone-beam views, 384^2 "
+                        "detector; 20 ordered subsets of 18 views, lambda 1",
+            "ms_per_iteration": ms, "ray_samples_per_s": 2 * S / (ms * 1e-3)}
+
+
 # ---------------------------------------------------------------------------
 # alternative workloads for profiling runs (one JSON line each)
 # ---------------------------------------------------------------------------
@@ -368,7 +428,8 @@ def main():
                     help="time the steps only (no auxiliary kernel figures): profiled runs")
     ap.add_argument("--only-aux", default="",
                     help="comma list of auxiliary figures to run (adjoint, dtypes (with the "
-                         "one-ray FP32 forward), naive, batched, t1, c5a, c5b); default all")
+                         "one-ray FP32 forward), naive, gd (20 gradient-descent steps, 512^3 "
+                         "only), batched, t1, c5a, c5b, sart); default all")
     ap.add_argument("--volume", default="phantom", choices=("phantom", "uniform"),
                     help="phantom: the workload's ellipsoid phantom (rasterised in FP64); "
                          "uniform: seeded uniform random values in [0, 1) drawn in FP32 "
@@ -456,7 +517,7 @@ def main():
                                "tile_v": tile, "launch_config": list(tile_cfg),
                                "pad_ms": r["pad"]["ms_per_launch"]}}
     want = set(a for a in args.only_aux.split(",") if a) or {
-        "adjoint", "dtypes", "naive", "batched", "t1", "c5a", "c5b"}
+        "adjoint", "dtypes", "naive", "gd", "batched", "t1", "c5a", "c5b", "sart"}
     if args.no_aux:
         want = set()
     if "adjoint" in want:
@@ -477,6 +538,8 @@ def main():
         _aux("storage_speedups", dts, kernels)
     if "naive" in want:
         _aux("forward_naive_f32", lambda: aux_naive(T, torch, gjp, G, x, S, fwd_ms), kernels)
+    if "gd" in want and cfg.name == "c3":
+        _aux("gd20_c3", lambda: aux_gd(T, torch, gjp, G, x), kernels)
     vol_np = None
     if not args.no_cpu_baseline:
         vol_np = x.cpu().numpy()
@@ -496,6 +559,8 @@ def main():
                                                   not args.no_autotune), kernels)
     if "batched" in want:
         _aux("batched_c4", lambda: aux_batched(T, torch, gjp, workloads, dev), kernels)
+    if "sart" in want:
+        _aux("sart_c2", lambda: aux_sart(torch, gjp, workloads, dev), kernels)
 
     out = {
         "metric": METRIC,

@@ -1604,6 +1604,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
   // acc_XYZ: voxel (x + X, y + Y, z + Z)
   float acc000 = 0.0f, acc001 = 0.0f, acc010 = 0.0f, acc011 = 0.0f;
   float acc100 = 0.0f, acc101 = 0.0f, acc110 = 0.0f, acc111 = 0.0f;
+  // The block's planes are x for driving axis 0 and y for axis 1: around the
+  // columns of axis 1 the accumulators of voxels (x + 1, y, .) and
+  // (x, y + 1, .) trade places, so that one plane/row mapping serves both axes
+  // (no per-column select).
+  auto swap_planes_rows = [&]() {
+    const float t0 = acc010, t1 = acc011;
+    acc010 = acc100;
+    acc011 = acc101;
+    acc100 = t0;
+    acc101 = t1;
+  };
   for (int c = c0; c < c0 + n_chunk; ++c) {
     const int mk = mask[c];
     if (!mk) continue;
@@ -1614,6 +1625,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
     const float* RV = VAL ? vals + (size_t)c * n_u * pitch : nullptr;
     for (int m = 0; m < 2; ++m) {
       if (!(mk & (1 << m))) continue;
+      if (m == 1) swap_planes_rows();
       const int va = (m == 0) ? y : x;  // first of the two in-plane rows
       const float fva = (float)va;
       const float ha = (m == 0) ? G.hi[1] : G.hi[0];
@@ -1808,18 +1820,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void a
           }
         }
         // block voxel (plane p0 + d, row va + r, z + k) gets wA<d><r> s<d><k>
-        if (m == 0) {
-          acc000 = __builtin_fmaf(wA00, s00, acc000); acc001 = __builtin_fmaf(wA00, s01, acc001);
-          acc010 = __builtin_fmaf(wA01, s00, acc010); acc011 = __builtin_fmaf(wA01, s01, acc011);
-          acc100 = __builtin_fmaf(wA10, s10, acc100); acc101 = __builtin_fmaf(wA10, s11, acc101);
-          acc110 = __builtin_fmaf(wA11, s10, acc110); acc111 = __builtin_fmaf(wA11, s11, acc111);
-        } else {
-          acc000 = __builtin_fmaf(wA00, s00, acc000); acc001 = __builtin_fmaf(wA00, s01, acc001);
-          acc100 = __builtin_fmaf(wA01, s00, acc100); acc101 = __builtin_fmaf(wA01, s01, acc101);
-          acc010 = __builtin_fmaf(wA10, s10, acc010); acc011 = __builtin_fmaf(wA10, s11, acc011);
-          acc110 = __builtin_fmaf(wA11, s10, acc110); acc111 = __builtin_fmaf(wA11, s11, acc111);
-        }
+        acc000 = __builtin_fmaf(wA00, s00, acc000); acc001 = __builtin_fmaf(wA00, s01, acc001);
+        acc010 = __builtin_fmaf(wA01, s00, acc010); acc011 = __builtin_fmaf(wA01, s01, acc011);
+        acc100 = __builtin_fmaf(wA10, s10, acc100); acc101 = __builtin_fmaf(wA10, s11, acc101);
+        acc110 = __builtin_fmaf(wA11, s10, acc110); acc111 = __builtin_fmaf(wA11, s11, acc111);
       }
+      if (m == 1) swap_planes_rows();
     }
   }
   if (!zin) return;
