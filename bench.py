@@ -227,6 +227,15 @@ def aux_naive(T, torch, gjp, G, x, S, fwd_ms):
     return {"ms": ms, "ray_samples_per_s": S / (ms * 1e-3), "tuned_f32_speedup": ms / fwd_ms}
 
 
+def autotune_instances(torch, gjp, geoms, vols, outs):
+    """The batched workload's ray-tile shapes: each instance's forward
+    autotuned on its own (untimed); the batched launch runs each instance's
+    choice. Returns the tile widths chosen."""
+    tiles = [gjp.autotune(v, G, o) for G, v, o in zip(geoms, vols, outs)]
+    torch.cuda.synchronize()
+    return tiles
+
+
 def aux_batched(T, torch, gjp, workloads, dev):
     from workloads.configs import batched_instances
     insts = batched_instances()
@@ -235,6 +244,9 @@ def aux_batched(T, torch, gjp, workloads, dev):
     S = sum(G.count_samples() for G in geoms)
     outs = [torch.empty(G.sino_shape, dtype=torch.float32, device=dev) for G in geoms]
     t0 = time.perf_counter()
+    tiles = autotune_instances(torch, gjp, geoms, vols, outs)
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
     gjp.forward_batched(vols, geoms, outs)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
@@ -242,9 +254,12 @@ def aux_batched(T, torch, gjp, workloads, dev):
     r = T.run(lambda: gjp.forward_batched(vols, geoms, outs), 3, ("batched",))
     ms = r["batched"]["ms_per_launch"]
     return {"workload": "c4: 32 uneven instances (edges 96-320, 90-360 views, 128^2-512^2 "
-                        "detectors, cone or parallel) in one persistent graph-replayed launch",
+                        "detectors, cone or parallel) in one persistent graph-replayed launch, "
+                        "each instance's ray-tile shape autotuned",
             "ms": ms, "wall_ms": r["wall_ms"], "ray_samples": S,
-            "ray_samples_per_s": S / (ms * 1e-3), "first_call_with_plan_s": plan_s}
+            "ray_samples_per_s": S / (ms * 1e-3), "first_call_with_plan_s": plan_s,
+            "autotune_s": tune_s,
+            "tile_v_counts": {str(t): tiles.count(t) for t in sorted(set(tiles))}}
 
 
 def aux_t1(T, torch, gjp, workloads, dev, autotune):

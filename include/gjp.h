@@ -157,8 +157,12 @@ gjp_status gjp_back_project(const gjp_geometry *g, const float *d_sino, float *d
    double-precision sample count of a few rays per tile (groups of views of
    one tile stay together); the launch sequence is captured in a HIP graph on
    first use for a given list of geometries and replayed afterwards. Each
-   sinogram is bitwise equal to the one gjp_forward_project produces for the
-   same instance and tile shape. Arrays g, d_vols, dtypes, d_sinos are host
+   instance runs its tuned tile shape (gjp_autotune_forward /
+   gjp_set_forward_tile; a two-rays-per-lane choice runs as the one-ray tile,
+   whose sums are the same); instances with three rays per lane form classes
+   of their own, one persistent launch per class. Each sinogram is bitwise
+   equal to the one gjp_forward_project produces for the same instance and
+   tile shape. Arrays g, d_vols, dtypes, d_sinos are host
    arrays of length n >= 1; every d_sinos[i] holds n_views*n_u*n_v floats.
    Calls with the same geometry list share one plan (its device descriptors,
    padded copies and queue counters); a call on any stream waits on the device

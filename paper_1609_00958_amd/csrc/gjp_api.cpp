@@ -727,7 +727,7 @@ void fill_fwd_args(const gjp_geometry* g, const double* d_views, const void* pad
   // k = 7: 128 pixels along v per wavefront row (two per lane), four rows;
   // k = 8: 192 pixels (three per lane), four rows
   const int tile_v = gjp::tile_v_pixels(tile.tile_v_log2);
-  const int tile_u = tile.tile_v_log2 >= 7 ? 4 : 256 >> tile.tile_v_log2;
+  const int tile_u = gjp::tile_u_columns(tile.tile_v_log2);
   a.tiles_v = (g->n_v + tile_v - 1) / tile_v;
   a.tiles_u = (g->n_u + tile_u - 1) / tile_u;
   a.tiles_per_view = a.tiles_v * a.tiles_u;
@@ -1108,7 +1108,7 @@ struct WorkGroup {
 
 // Estimated samples of each work group: the exact sample counts (the kernels'
 // own double-precision ray setup) of five rays per tile and view -- its four
-// corner pixels and its centre -- scaled to the tile's 256 rays, plus a fixed
+// corner pixels and its centre -- scaled to the tile's rays, plus a fixed
 // per-ray setup cost.
 void estimate_group_costs(const gjp_geometry* const* g, const std::vector<BatchInst>& insts,
                           std::vector<WorkGroup>& groups) {
@@ -1122,10 +1122,11 @@ void estimate_group_costs(const gjp_geometry* const* g, const std::vector<BatchI
       const gjp_geometry* G = g[w.inst];
       const FwdArgs& a = insts[w.inst].a;
       const int kv = a.tile_v_log2;
+      const int tile_u = gjp::tile_u_columns(kv), tile_v = gjp::tile_v_pixels(kv);
       const int tu = w.tile / a.tiles_v, tv = w.tile - tu * a.tiles_v;
-      const int u_lo = tu * (256 >> kv), v_lo = tv << kv;
-      const int u_hi = std::min(G->n_u, u_lo + (256 >> kv)) - 1;
-      const int v_hi = std::min(G->n_v, v_lo + (1 << kv)) - 1;
+      const int u_lo = tu * tile_u, v_lo = tv * tile_v;
+      const int u_hi = std::min(G->n_u, u_lo + tile_u) - 1;
+      const int v_hi = std::min(G->n_v, v_lo + tile_v) - 1;
       const int pu[5] = {u_lo, u_lo, u_hi, u_hi, (u_lo + u_hi) / 2};
       const int pv[5] = {v_lo, v_hi, v_lo, v_hi, (v_lo + v_hi) / 2};
       const int kg = std::min(std::max(1, a.view_group), G->n_views - w.v0);
@@ -1176,8 +1177,9 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
     const FwdTile tile = tile_for(g[i], dtypes[i]);
     FwdTile t2 = tile;
     t2.remap = 0;
-    // the batched launch runs one ray per lane (same sums as two per lane)
-    if (t2.tile_v_log2 > 6) t2.tile_v_log2 = 6;
+    // the batched launch runs the tuned tile with one or three rays per lane;
+    // a tuned two-rays-per-lane tile becomes the one-ray tile (same sums)
+    if (t2.tile_v_log2 == 7) t2.tile_v_log2 = 6;
     fill_fwd_args(g[i], d_views, nullptr, nullptr, t2, I.a);
     I.padded = static_cast<char*>(P->padded_all) + pad_off[i];
     set_padded(I.a, I.padded, dtypes[i], g[i]->n);
@@ -1222,7 +1224,8 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
     const size_t begin = items.size();
     for (const auto& w : groups) {
       const BatchInst& I = P->host[w.inst];
-      if (gjp::batch_class(I.dtype, I.weight, I.idx64) != c) continue;
+      if (gjp::batch_class(I.dtype, I.weight, I.idx64, I.a.tile_v_log2 == 8 ? 1 : 0) != c)
+        continue;
       const int kg = std::min(std::max(1, I.a.view_group), I.n_views - w.v0);
       for (int v = w.v0; v < w.v0 + kg; ++v)
         items.push_back(make_uint2((uint32_t)w.inst | ((uint32_t)v << 12), (uint32_t)w.tile));

@@ -132,17 +132,22 @@ struct BatchInst {
   long long padded_elems;
 };
 int launch_batched_pad(const BatchInst* d_insts, int n_inst, hipStream_t s);
-// Instance class of the batched launch: (dtype * 2 + weight) * 2 + idx64.
-inline int batch_class(int dtype, int weight, int idx64) { return (dtype * 2 + weight) * 2 + idx64; }
-constexpr int kBatchClasses = 12;
+// Instance class of the batched launch: storage type, weight, 64-bit
+// addressing and three rays per lane (192-wide tiles) or one.
+inline int batch_class(int dtype, int weight, int idx64, int triple) {
+  return ((dtype * 2 + weight) * 2 + idx64) * 2 + triple;
+}
+constexpr int kBatchClasses = 24;
 int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
                            int* counter, int grid, int cls, hipStream_t s);
 int batched_grid_size(int cls);
 
 size_t dtype_size(int dtype);
 
-// Detector pixels along v per wavefront row of a forward tile code.
+// Detector pixels along v per wavefront row of a forward tile code, and
+// detector columns per workgroup tile.
 inline int tile_v_pixels(int tile_v_log2) { return tile_v_log2 == 8 ? 192 : 1 << tile_v_log2; }
+inline int tile_u_columns(int tile_v_log2) { return tile_v_log2 >= 7 ? 4 : 256 >> tile_v_log2; }
 
 // Fixed device scratch of gjp_forward_project_noalloc (gjp_kernels.hip): its
 // size, and its address on the current device (looked up once per device).

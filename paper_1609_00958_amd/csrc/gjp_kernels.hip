@@ -1885,12 +1885,12 @@ __global__ void zero_ints_kernel(int* p, int n) {
 }
 
 // Persistent batched forward for one instance class (storage type T, weight
-// WF, addressing IDX64): each workgroup pulls (instance, view, tile) items
-// from the class's queue until it is drained.
-template <typename T, int WF, bool IDX64>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void batched_fwd_kernel(const BatchInst* __restrict__ insts,
-                                                          const uint2* __restrict__ items,
-                                                          int n_items, int* __restrict__ counter) {
+// WF, addressing IDX64, rays per lane RPL): each workgroup pulls (instance,
+// view, tile) items from the class's queue until it is drained.
+template <typename T, int WF, bool IDX64, int RPL>
+__device__ __forceinline__ void batched_loop(const BatchInst* __restrict__ insts,
+                                             const uint2* __restrict__ items, int n_items,
+                                             int* __restrict__ counter) {
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -1901,8 +1901,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void b
     const uint2 it = items[item];
     const int inst = (int)(it.x & 0xfffu);
     const int view = (int)(it.x >> 12);
-    fwd_tile<T, WF, IDX64, kBatchRuGroup, false>(insts[inst].a, view, (int)it.y);
+    fwd_tile<T, WF, IDX64, kBatchRuGroup, RPL>(insts[inst].a, view, (int)it.y);
   }
+}
+
+// One ray per lane (tiles of 64, 32 or 16 pixels along v).
+template <typename T, int WF, bool IDX64>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void batched_fwd_kernel(
+    const BatchInst* __restrict__ insts, const uint2* __restrict__ items, int n_items,
+    int* __restrict__ counter) {
+  batched_loop<T, WF, IDX64, 1>(insts, items, n_items, counter);
+}
+
+// Three rays per lane (192-wide tiles): the instances whose tuned tile is the
+// three-rays-per-lane one; a kernel of its own, as in the single launch, so
+// that the one-ray class keeps its occupancy.
+template <typename T, int WF, bool IDX64>
+__global__ __launch_bounds__(256) void batched_fwd_triple_kernel(
+    const BatchInst* __restrict__ insts, const uint2* __restrict__ items, int n_items,
+    int* __restrict__ counter) {
+  batched_loop<T, WF, IDX64, 3>(insts, items, n_items, counter);
 }
 
 // ---------------------------------------------------------------------------
@@ -2183,37 +2201,51 @@ int launch_zero_ints(int* p, int n, hipStream_t s) {
   return check_launch("zero kernel");
 }
 
-template <typename T, int WF, bool IDX64>
-static int batched_grid_t() {
+// Resident workgroups of a persistent kernel on the whole device.
+static int persistent_grid(const void* kernel) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_fwd_kernel<T, WF, IDX64>, 256,
-                                                   0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess ||
       per <= 0)
     per = 4;
   return cus * per;
 }
 
-template <typename T, int WF, bool IDX64>
-static void launch_batched_t(const BatchInst* d_insts, const uint2* d_items, int n_items,
-                             int* counter, int grid, hipStream_t s) {
-  batched_fwd_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, n_items, counter);
+template <typename T, int WF, bool IDX64, bool TRIPLE>
+static int batched_grid_t() {
+  if constexpr (TRIPLE)
+    return persistent_grid(reinterpret_cast<const void*>(batched_fwd_triple_kernel<T, WF, IDX64>));
+  else
+    return persistent_grid(reinterpret_cast<const void*>(batched_fwd_kernel<T, WF, IDX64>));
 }
 
-// class = (dtype * 2 + weight) * 2 + idx64
-#define GJP_BATCH_CLASSES(X)                                                        \
-  X(0, float, W_LINEAR, false) X(1, float, W_LINEAR, true) X(2, float, W_SPLINE, false) \
-  X(3, float, W_SPLINE, true) X(4, bf16_t, W_LINEAR, false) X(5, bf16_t, W_LINEAR, true) \
-  X(6, bf16_t, W_SPLINE, false) X(7, bf16_t, W_SPLINE, true) X(8, f16_t, W_LINEAR, false) \
-  X(9, f16_t, W_LINEAR, true) X(10, f16_t, W_SPLINE, false) X(11, f16_t, W_SPLINE, true)
+template <typename T, int WF, bool IDX64, bool TRIPLE>
+static void launch_batched_t(const BatchInst* d_insts, const uint2* d_items, int n_items,
+                             int* counter, int grid, hipStream_t s) {
+  if constexpr (TRIPLE)
+    batched_fwd_triple_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, n_items,
+                                                                 counter);
+  else
+    batched_fwd_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, n_items, counter);
+}
+
+// class = ((dtype * 2 + weight) * 2 + idx64) * 2 + triple (batch_class)
+#define GJP_BATCH_CLASSES_RPL(X, R, o)                                                      \
+  X(o + 0, float, W_LINEAR, false, R) X(o + 2, float, W_LINEAR, true, R)                    \
+  X(o + 4, float, W_SPLINE, false, R) X(o + 6, float, W_SPLINE, true, R)                    \
+  X(o + 8, bf16_t, W_LINEAR, false, R) X(o + 10, bf16_t, W_LINEAR, true, R)                 \
+  X(o + 12, bf16_t, W_SPLINE, false, R) X(o + 14, bf16_t, W_SPLINE, true, R)                \
+  X(o + 16, f16_t, W_LINEAR, false, R) X(o + 18, f16_t, W_LINEAR, true, R)                  \
+  X(o + 20, f16_t, W_SPLINE, false, R) X(o + 22, f16_t, W_SPLINE, true, R)
+#define GJP_BATCH_CLASSES(X) GJP_BATCH_CLASSES_RPL(X, false, 0) GJP_BATCH_CLASSES_RPL(X, true, 1)
 
 int batched_grid_size(int cls) {
   switch (cls) {
-#define GJP_CASE(k, T, W, I) \
-  case k:                    \
-    return batched_grid_t<T, W, I>();
+#define GJP_CASE(k, T, W, I, R) \
+  case k:                       \
+    return batched_grid_t<T, W, I, R>();
     GJP_BATCH_CLASSES(GJP_CASE)
 #undef GJP_CASE
     default:
@@ -2224,9 +2256,9 @@ int batched_grid_size(int cls) {
 int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
                            int* counter, int grid, int cls, hipStream_t s) {
   switch (cls) {
-#define GJP_CASE(k, T, W, I)                                               \
-  case k:                                                                  \
-    launch_batched_t<T, W, I>(d_insts, d_items, n_items, counter, grid, s); \
+#define GJP_CASE(k, T, W, I, R)                                               \
+  case k:                                                                     \
+    launch_batched_t<T, W, I, R>(d_insts, d_items, n_items, counter, grid, s); \
     break;
     GJP_BATCH_CLASSES(GJP_CASE)
 #undef GJP_CASE

@@ -147,6 +147,42 @@ def test_batched_full_c4_instances(gjp, oracle_mod):
         assert_parity(got, want, 1e-5)
 
 
+def test_batched_tuned_tiles(gjp, oracle_mod):
+    """Instances of the uneven workload with set tile shapes (three rays per
+    lane, one ray, two rays per lane for 16-bit storage) in one batched
+    launch: the three-rays-per-lane instances run in classes of their own;
+    every sinogram equals the single-instance forward with the same tile bit
+    for bit (capture and replay) and matches the oracle on sampled rays."""
+    import torch
+    from workloads.configs import batched_instances
+    dev = cuda()
+    insts = batched_instances()[:6]
+    dts = [torch.float32, torch.bfloat16, torch.float16, torch.float32, torch.float16,
+           torch.bfloat16]
+    tiles = [(192, 8, 4), (64, 8, 4), (128, 16, 4), (192, 16, 2), (192, 1, 4), (64, 16, 2)]
+    geoms = [gjp.Geometry.from_config(cfg) for cfg in insts]
+    vols = [workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev).to(dt)
+            for cfg, dt in zip(insts, dts)]
+    try:
+        for G, dt, t in zip(geoms, dts, tiles):
+            gjp.set_forward_tile(G, dt, *t)
+        for rep in range(2):
+            note(f"batched tuned tiles: rep {rep}")
+            outs = gjp.forward_batched(vols, geoms)
+            torch.cuda.synchronize()
+            for k, (cfg, G, v, o) in enumerate(zip(insts, geoms, vols, outs)):
+                assert torch.equal(o, gjp.forward(v, G)), (k, tiles[k])
+        for k, (cfg, v, o) in enumerate(zip(insts, vols, outs)):
+            rays = workloads.sample_rays(700 + k, 150, cfg.n_views, cfg.n_u, cfg.n_v)
+            got = o.cpu().numpy()[rays[:, 0], rays[:, 1], rays[:, 2]]
+            want = oracle_mod.forward_rays(oracle_mod.geometry_for(cfg),
+                                           v.float().cpu().numpy(), rays)
+            assert_parity(got, want, 1e-5)
+    finally:
+        for G, dt in zip(geoms, dts):
+            gjp.set_forward_tile(G, dt, 0, 1, 4)
+
+
 # ---------------------------------------------------------------------------
 # autograd wrapper: gradient = adjoint; central differences of the quadratic loss
 # ---------------------------------------------------------------------------
