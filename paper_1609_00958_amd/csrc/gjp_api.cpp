@@ -966,7 +966,7 @@ extern "C" gjp_status gjp_get_forward_tile(const gjp_geometry* g, int32_t vol_dt
 // adjoint
 // ---------------------------------------------------------------------------
 // Views per launch of the column-form gather (see gjp_back_project).
-static const int kGatherViews = 16;
+static const int kGatherViews = 32;
 
 extern "C" gjp_status gjp_back_project(const gjp_geometry* g, const float* d_sino, float* d_vol,
                                        void* stream) {
