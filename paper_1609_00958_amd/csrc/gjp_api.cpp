@@ -1123,7 +1123,7 @@ void estimate_group_costs(const gjp_geometry* const* g, const std::vector<BatchI
       const FwdArgs& a = insts[w.inst].a;
       const int kv = a.tile_v_log2;
       const int tile_u = gjp::tile_u_columns(kv), tile_v = gjp::tile_v_pixels(kv);
-      const int tu = w.tile / a.tiles_v, tv = w.tile - tu * a.tiles_v;
+      const int tv = w.tile / a.tiles_u, tu = w.tile - tv * a.tiles_u;  // the kernels' order
       const int u_lo = tu * tile_u, v_lo = tv * tile_v;
       const int u_hi = std::min(G->n_u, u_lo + tile_u) - 1;
       const int v_hi = std::min(G->n_v, v_lo + tile_v) - 1;

@@ -989,10 +989,15 @@ __device__ __forceinline__ void fwd_ray_triple(const FwdArgs& a, int view, int i
 
 // RPL: rays per lane (1; 2 in 128-wide tiles or 3 in 192-wide tiles, 16-bit
 // storage).
+// Tile t of a view: consecutive tiles are neighbouring column groups of one
+// band of detector rows (v), so the workgroups that run together on an XCD
+// read neighbouring voxel rows of the same axis-2 range and share them in L2
+// (c3 FP32 forward 83.5 -> 69.3 ms against row bands taken one after another
+// within a column group; bitwise the same sums).
 template <typename T, int WF, bool IDX64, int GRP, int RPL>
 __device__ __forceinline__ void fwd_tile(const FwdArgs& a, int view, int t) {
-  const int tu = t / a.tiles_v;
-  const int tv = t - tu * a.tiles_v;
+  const int tv = t / a.tiles_u;
+  const int tu = t - tv * a.tiles_u;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int k = a.tile_v_log2;
