@@ -206,9 +206,9 @@ gjp_status gjp_count_samples(const gjp_geometry *g, uint64_t *out);
    count; replaced atomically by rename) and later processes on the same kind
    of device read it instead of the default; an unreadable or unwritable
    file is ignored. *tile_v_out receives the chosen number of detector pixels
-   along v per wavefront row (64, 32 or 16; 128 or 192 for 16-bit storage
-   when two or three pixels per lane share their loads). Synchronises
-   `stream`.
+   along v per wavefront row (192 when three pixels per lane share their
+   loads, any storage type; 128 when two do, 16-bit storage only; else 64, 32
+   or 16). Synchronises `stream`.
    Errors: GJP_EINVAL, GJP_ENOMEM, GJP_EHIP. */
 gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_t vol_dtype,
                                 float *d_sino, void *stream, int32_t *tile_v_out);
@@ -216,11 +216,12 @@ gjp_status gjp_autotune_forward(const gjp_geometry *g, const void *d_vol, int32_
 /* Fix the launch configuration that forward calls (and, for the tile shape
    and view group, batched calls) use in this process for geometries of this
    shape signature and dtype, as gjp_autotune_forward would: tile_v =
-   detector pixels along v per wavefront row (64, 32 or 16, or for 16-bit
-   storage 128 or 192: two or three pixels of a detector column per lane,
-   sharing their loads where the geometry allows, with 192 interpolating
-   each element along the row first, equal to the other tiles' sums up to
-   rounding; batched calls take 64 for them); view_group =
+   detector pixels along v per wavefront row (64, 32 or 16; 192: three
+   pixels of a detector column per lane, any storage type; 128: two, 16-bit
+   storage only; the pixels of a lane share their loads where the geometry
+   allows; 192 interpolates each element along the row first, equal to the
+   other tiles' sums up to rounding; batched calls run 128 as 64, whose sums
+   are the same); view_group =
    consecutive views that take their turn on each ray tile together (1 to
    64); load_group = planes whose volume loads a lane issues together (2 or
    4). tile_v = 0 removes this process's choice (the on-disk cache or the

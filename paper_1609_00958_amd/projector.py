@@ -271,10 +271,11 @@ def autotune(vol, geom: Geometry, out=None) -> int:
 def set_forward_tile(geom: Geometry, dtype, tile_v: int, view_group: int = 8,
                      load_group: int = 4) -> None:
     """Fix the forward launch configuration for this geometry's shape signature
-    and a torch dtype: tile_v = 64, 32 or 16 detector pixels along v per
-    wavefront row (for 16-bit storage also 128 or 192: two or three pixels
-    per lane sharing their loads), view_group views per tile turn (1..64),
-    load_group planes whose loads a lane issues together (2 or 4)."""
+    and a torch dtype: tile_v = 192 (three pixels per lane sharing their
+    loads), 64, 32 or 16 detector pixels along v per wavefront row (for 16-bit
+    storage also 128: two pixels per lane), view_group views per tile turn
+    (1..64), load_group planes whose loads a lane issues together (2 or 4);
+    tile_v = 0 forgets this process's choice."""
     torch = _torch()
     code = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}[dtype]
     check(lib().gjp_set_forward_tile(geom.handle, code, int(tile_v), int(view_group),
