@@ -300,16 +300,20 @@ def aux_c5a(T, torch, gjp, workloads, dev, tiles16):
     return res
 
 
-def aux_c5b(T, torch, gjp, workloads, dev):
+def aux_c5b(T, torch, gjp, workloads, dev, tile32):
     cfg = workloads.config("c5b")
     G = gjp.Geometry.from_config(cfg)
     S = G.count_samples()
     x = workloads.rasterize_torch(cfg.phantom_ellipsoids(), cfg.shape, dev)
     y = torch.empty(G.sino_shape, device=dev)
+    if tile32:
+        gjp.set_forward_tile(G, torch.float32, *tile32)
     gjp.forward(x, G, y)
     r = T.run(lambda: gjp.forward(x, G, y), 1, ("forward", "pad"))
     ms = r["forward"]["ms_per_launch"]
-    return {"workload": "c5b: 2048^3 FP32 (34 GB), 64 cone-beam views, 3072^2 detector",
+    return {"workload": "c5b: 2048^3 FP32 (34 GB), 64 cone-beam views, 3072^2 detector; "
+                        "launch configuration of the 512^3 autotuning",
+            "launch_config": list(gjp.get_forward_tile(G, torch.float32)),
             "ms": ms, "pad_ms": r["pad"]["ms_per_launch"], "ray_samples": S,
             "ray_samples_per_s": S / (ms * 1e-3)}
 
@@ -562,7 +566,8 @@ def main():
     torch.cuda.empty_cache()
     # the largest workloads first, while the device holds nothing else
     if "c5b" in want:
-        _aux("c5b_2048_f32", lambda: aux_c5b(T, torch, gjp, workloads, dev), kernels)
+        tile32 = tuple(tile_cfg) if tile else None
+        _aux("c5b_2048_f32", lambda: aux_c5b(T, torch, gjp, workloads, dev, tile32), kernels)
     if "c5a" in want:
         tiles16 = {}
         for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):

@@ -269,10 +269,11 @@ def test_gradient_descent_monotone(gjp):
 # ---------------------------------------------------------------------------
 # full-size configurations in the benchmark's launch setup, on sampled rays
 # ---------------------------------------------------------------------------
-def _full_config_check(gjp, oracle_mod, name, n_rays, dtypes=("f32",), pairs=False):
+def _full_config_check(gjp, oracle_mod, name, n_rays, dtypes=("f32",), pairs=False, tiles=()):
     """Sampled rays of the full workload against the oracle; with pairs, every
     16-bit sinogram of the two-rays-per-lane tile is also compared bit for bit
-    with the one-ray tile's."""
+    with the one-ray tile's; tiles: further launch configurations (tile_v,
+    view group, load group) checked against the oracle on the same rays."""
     import torch
     dev = cuda()
     cfg = workloads.config(name)
@@ -310,6 +311,13 @@ def _full_config_check(gjp, oracle_mod, name, n_rays, dtypes=("f32",), pairs=Fal
             gjp.set_forward_tile(G, tdt, 64, 8, 4)
             assert_parity(y3[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy(), want, 1e-5)
             del y3
+        for t in tiles:
+            note(f"{name}: forward {dt}, launch configuration {t}")
+            gjp.set_forward_tile(G, tdt, *t)
+            yt = gjp.forward(xd, G)
+            gjp.set_forward_tile(G, tdt, 0, 1, 4)
+            assert_parity(yt[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy(), want, 1e-5)
+            del yt
         if dt != "f32":
             want32 = oracle_mod.forward_rays(og, x.cpu().numpy(), rays)
             assert_parity(got, want32, 5e-3)
@@ -360,8 +368,10 @@ def test_full_c5a_forward_16bit(gjp, oracle_mod):
 @pytest.mark.slow
 def test_full_c5b_forward_2048(gjp, oracle_mod):
     """2048^3 FP32 (34 GB, 64-bit offsets), 64 views, 3072^2 detector, checked on
-    sampled rays against the oracle reading the same volume on the host."""
-    _full_config_check(gjp, oracle_mod, "c5b", 1500)
+    sampled rays against the oracle reading the same volume on the host, with
+    the default one-ray tile and with three rays per lane (the benchmark's
+    configuration)."""
+    _full_config_check(gjp, oracle_mod, "c5b", 1500, tiles=[(192, 8, 4)])
 
 
 def _analytic_sinogram_torch(cfg, G, dev):
