@@ -153,9 +153,9 @@ gjp_status gjp_back_project(const gjp_geometry *g, const float *d_sino, float *d
 
 /* Batched forward projection of n independent instances (geometry, volume,
    dtype, sinogram) in one persistent launch: work items (instance, view, ray
-   tile) are pulled from a device queue, longest first by the host
-   double-precision sample count of a few rays per tile (groups of views of
-   one tile stay together); the launch sequence is captured in a HIP graph on
+   tile) are pulled from device queues (one per XCD, dealt whole groups of
+   views of one tile at a time), longest first by the host double-precision
+   sample count of a few rays per tile; the launch sequence is captured in a HIP graph on
    first use for a given list of geometries and replayed afterwards. Each
    instance runs its tuned tile shape (gjp_autotune_forward /
    gjp_set_forward_tile; a two-rays-per-lane choice runs as the one-ray tile,

@@ -1046,7 +1046,8 @@ struct BatchPlan {
   std::vector<BatchInst> host;  // descriptors without per-call pointers
   BatchInst* d_insts = nullptr;
   uint2* d_items = nullptr;
-  int* d_counter = nullptr;
+  int* d_counter = nullptr;  // kBatchQueues per class
+  int* d_qoff = nullptr;     // kBatchQueues + 1 per class
   void* padded_all = nullptr;
   int n_items = 0;
   // items are grouped by instance class; one persistent launch per class
@@ -1078,6 +1079,7 @@ struct BatchPlan {
     if (d_insts) (void)hipFree(d_insts);
     if (d_items) (void)hipFree(d_items);
     if (d_counter) (void)hipFree(d_counter);
+    if (d_qoff) (void)hipFree(d_qoff);
     if (padded_all) (void)hipFree(padded_all);
     if (staging) (void)hipHostFree(staging);
     if (cur >= 0) (void)hipSetDevice(cur);
@@ -1220,22 +1222,36 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
   } catch (...) {
     return fail(GJP_ENOMEM, "batched: work list");
   }
+  // Per class, the groups go round robin to kBatchQueues queues (one per XCD),
+  // each keeping the longest-first order; a group's items stay together.
+  std::vector<int> qoff;
   for (int c = 0; c < gjp::kBatchClasses; ++c) {
     const size_t begin = items.size();
-    for (const auto& w : groups) {
-      const BatchInst& I = P->host[w.inst];
-      if (gjp::batch_class(I.dtype, I.weight, I.idx64, I.a.tile_v_log2 == 8 ? 1 : 0) != c)
-        continue;
-      const int kg = std::min(std::max(1, I.a.view_group), I.n_views - w.v0);
-      for (int v = w.v0; v < w.v0 + kg; ++v)
-        items.push_back(make_uint2((uint32_t)w.inst | ((uint32_t)v << 12), (uint32_t)w.tile));
+    std::vector<std::vector<uint2>> q(gjp::kBatchQueues);
+    int gi = 0;
+    try {
+      for (const auto& w : groups) {
+        const BatchInst& I = P->host[w.inst];
+        if (gjp::batch_class(I.dtype, I.weight, I.idx64, I.a.tile_v_log2 == 8 ? 1 : 0) != c)
+          continue;
+        std::vector<uint2>& dst = q[gi++ % gjp::kBatchQueues];
+        const int kg = std::min(std::max(1, I.a.view_group), I.n_views - w.v0);
+        for (int v = w.v0; v < w.v0 + kg; ++v)
+          dst.push_back(make_uint2((uint32_t)w.inst | ((uint32_t)v << 12), (uint32_t)w.tile));
+      }
+    } catch (...) {
+      return fail(GJP_ENOMEM, "batched: queues");
     }
-    if (items.size() > begin) {
-      P->cls.push_back(c);
-      P->cls_begin.push_back((int)begin);
-      P->cls_count.push_back((int)(items.size() - begin));
-      P->cls_grid.push_back(gjp::batched_grid_size(c));
+    if (gi == 0) continue;
+    for (int x = 0; x < gjp::kBatchQueues; ++x) {
+      qoff.push_back((int)(items.size() - begin));
+      items.insert(items.end(), q[x].begin(), q[x].end());
     }
+    qoff.push_back((int)(items.size() - begin));
+    P->cls.push_back(c);
+    P->cls_begin.push_back((int)begin);
+    P->cls_count.push_back((int)(items.size() - begin));
+    P->cls_grid.push_back(gjp::batched_grid_size(c));
   }
   P->n_items = (int)items.size();
   GJP_HIP(hipMalloc(&P->d_items, std::max<size_t>(1, items.size()) * sizeof(uint2)),
@@ -1244,8 +1260,13 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
                     hipMemcpyHostToDevice),
           "batched: items copy");
   GJP_HIP(hipMalloc(&P->d_insts, (size_t)n * sizeof(BatchInst)), "batched: descriptors");
-  GJP_HIP(hipMalloc(&P->d_counter, std::max<size_t>(1, P->cls.size()) * sizeof(int)),
-          "batched: queues");
+  const size_t n_cls = std::max<size_t>(1, P->cls.size());
+  GJP_HIP(hipMalloc(&P->d_counter, n_cls * gjp::kBatchQueues * sizeof(int)), "batched: queues");
+  GJP_HIP(hipMalloc(&P->d_qoff, n_cls * (gjp::kBatchQueues + 1) * sizeof(int)),
+          "batched: queue offsets");
+  if (!qoff.empty())
+    GJP_HIP(hipMemcpy(P->d_qoff, qoff.data(), qoff.size() * sizeof(int), hipMemcpyHostToDevice),
+            "batched: queue offsets copy");
   GJP_HIP(hipHostMalloc(&P->staging, (size_t)n * sizeof(BatchInst), 0), "batched: staging");
   GJP_HIP(hipEventCreateWithFlags(&P->staged, hipEventDisableTiming), "batched: event");
   GJP_HIP(hipEventCreateWithFlags(&P->done, hipEventDisableTiming), "batched: event");
@@ -1256,10 +1277,12 @@ gjp_status build_plan(int n, const gjp_geometry* const* g, const int32_t* dtypes
   int st = GJP_OK;
   if (e == hipSuccess) {
     st = gjp::launch_batched_pad(P->d_insts, n, cap);
-    if (st == GJP_OK) st = gjp::launch_zero_ints(P->d_counter, (int)P->cls.size(), cap);
+    if (st == GJP_OK)
+      st = gjp::launch_zero_ints(P->d_counter, (int)P->cls.size() * gjp::kBatchQueues, cap);
     for (size_t k = 0; k < P->cls.size() && st == GJP_OK; ++k)
       st = gjp::launch_batched_forward(P->d_insts, P->d_items + P->cls_begin[k],
-                                       P->cls_count[k], P->d_counter + k, P->cls_grid[k],
+                                       P->d_qoff + k * (gjp::kBatchQueues + 1),
+                                       P->d_counter + k * gjp::kBatchQueues, P->cls_grid[k],
                                        P->cls[k], cap);
     const hipError_t e2 = hipStreamEndCapture(cap, &P->graph);
     if (e2 != hipSuccess && st == GJP_OK) st = hip_fail(e2, "batched: end capture");

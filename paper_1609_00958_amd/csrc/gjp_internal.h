@@ -138,8 +138,12 @@ inline int batch_class(int dtype, int weight, int idx64, int triple) {
   return ((dtype * 2 + weight) * 2 + idx64) * 2 + triple;
 }
 constexpr int kBatchClasses = 24;
-int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
-                           int* counter, int grid, int cls, hipStream_t s);
+// Queues per class of the batched launch: one per XCD.
+constexpr int kBatchQueues = 8;
+// One class's persistent launch: items of its kBatchQueues queues, queue q =
+// d_items[d_qoff[q] .. d_qoff[q + 1]), counters d_counters[0 .. kBatchQueues).
+int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, const int* d_qoff,
+                           int* d_counters, int grid, int cls, hipStream_t s);
 int batched_grid_size(int cls);
 
 size_t dtype_size(int dtype);

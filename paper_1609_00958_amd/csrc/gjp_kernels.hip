@@ -1890,32 +1890,44 @@ __global__ void zero_ints_kernel(int* p, int n) {
 }
 
 // Persistent batched forward for one instance class (storage type T, weight
-// WF, addressing IDX64, rays per lane RPL): each workgroup pulls (instance,
-// view, tile) items from the class's queue until it is drained.
+// WF, addressing IDX64, rays per lane RPL). The class's items come in
+// kBatchQueues queues, one per XCD, each holding whole view groups (a tile's
+// items for the group's views in turn) so that the views sharing volume lines
+// run on one XCD's L2: queue q is items [qoff[q], qoff[q + 1]) with counter
+// counters[q]. A workgroup drains the queue of the XCD it runs on (workgroups
+// are dispatched to the XCDs round robin), then helps with the others; every
+// counter only grows, so each workgroup leaves after at most one failed pull
+// per queue.
 template <typename T, int WF, bool IDX64, int RPL>
 __device__ __forceinline__ void batched_loop(const BatchInst* __restrict__ insts,
-                                             const uint2* __restrict__ items, int n_items,
-                                             int* __restrict__ counter) {
+                                             const uint2* __restrict__ items,
+                                             const int* __restrict__ qoff,
+                                             int* __restrict__ counters) {
   __shared__ int s_item;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-    __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
-    if (item >= n_items) break;
-    const uint2 it = items[item];
-    const int inst = (int)(it.x & 0xfffu);
-    const int view = (int)(it.x >> 12);
-    fwd_tile<T, WF, IDX64, kBatchRuGroup, RPL>(insts[inst].a, view, (int)it.y);
+  const int home = (int)(blockIdx.x % kBatchQueues);
+  for (int d = 0; d < kBatchQueues; ++d) {
+    const int q = (home + d) % kBatchQueues;
+    const int begin = qoff[q], n = qoff[q + 1] - begin;
+    for (;;) {
+      if (threadIdx.x == 0) s_item = atomicAdd(&counters[q], 1);
+      __syncthreads();
+      const int item = __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();
+      if (item >= n) break;
+      const uint2 it = items[begin + item];
+      const int inst = (int)(it.x & 0xfffu);
+      const int view = (int)(it.x >> 12);
+      fwd_tile<T, WF, IDX64, kBatchRuGroup, RPL>(insts[inst].a, view, (int)it.y);
+    }
   }
 }
 
 // One ray per lane (tiles of 64, 32 or 16 pixels along v).
 template <typename T, int WF, bool IDX64>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void batched_fwd_kernel(
-    const BatchInst* __restrict__ insts, const uint2* __restrict__ items, int n_items,
-    int* __restrict__ counter) {
-  batched_loop<T, WF, IDX64, 1>(insts, items, n_items, counter);
+    const BatchInst* __restrict__ insts, const uint2* __restrict__ items,
+    const int* __restrict__ qoff, int* __restrict__ counters) {
+  batched_loop<T, WF, IDX64, 1>(insts, items, qoff, counters);
 }
 
 // Three rays per lane (192-wide tiles): the instances whose tuned tile is the
@@ -1923,9 +1935,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void b
 // that the one-ray class keeps its occupancy.
 template <typename T, int WF, bool IDX64>
 __global__ __launch_bounds__(256) void batched_fwd_triple_kernel(
-    const BatchInst* __restrict__ insts, const uint2* __restrict__ items, int n_items,
-    int* __restrict__ counter) {
-  batched_loop<T, WF, IDX64, 3>(insts, items, n_items, counter);
+    const BatchInst* __restrict__ insts, const uint2* __restrict__ items,
+    const int* __restrict__ qoff, int* __restrict__ counters) {
+  batched_loop<T, WF, IDX64, 3>(insts, items, qoff, counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -2227,13 +2239,13 @@ static int batched_grid_t() {
 }
 
 template <typename T, int WF, bool IDX64, bool TRIPLE>
-static void launch_batched_t(const BatchInst* d_insts, const uint2* d_items, int n_items,
-                             int* counter, int grid, hipStream_t s) {
+static void launch_batched_t(const BatchInst* d_insts, const uint2* d_items, const int* qoff,
+                             int* counters, int grid, hipStream_t s) {
   if constexpr (TRIPLE)
-    batched_fwd_triple_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, n_items,
-                                                                 counter);
+    batched_fwd_triple_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, qoff,
+                                                                 counters);
   else
-    batched_fwd_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, n_items, counter);
+    batched_fwd_kernel<T, WF, IDX64><<<grid, 256, 0, s>>>(d_insts, d_items, qoff, counters);
 }
 
 // class = ((dtype * 2 + weight) * 2 + idx64) * 2 + triple (batch_class)
@@ -2258,12 +2270,12 @@ int batched_grid_size(int cls) {
   }
 }
 
-int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, int n_items,
-                           int* counter, int grid, int cls, hipStream_t s) {
+int launch_batched_forward(const BatchInst* d_insts, const uint2* d_items, const int* d_qoff,
+                           int* d_counters, int grid, int cls, hipStream_t s) {
   switch (cls) {
-#define GJP_CASE(k, T, W, I, R)                                               \
-  case k:                                                                     \
-    launch_batched_t<T, W, I, R>(d_insts, d_items, n_items, counter, grid, s); \
+#define GJP_CASE(k, T, W, I, R)                                                 \
+  case k:                                                                       \
+    launch_batched_t<T, W, I, R>(d_insts, d_items, d_qoff, d_counters, grid, s); \
     break;
     GJP_BATCH_CLASSES(GJP_CASE)
 #undef GJP_CASE

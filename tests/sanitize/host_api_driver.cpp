@@ -43,7 +43,8 @@ int launch_adjoint_value_table(const gjp_geometry*, const double*, const float*,
   return stub("value table");
 }
 int launch_batched_pad(const BatchInst*, int, hipStream_t) { return stub("batched pad"); }
-int launch_batched_forward(const BatchInst*, const uint2*, int, int*, int, int, hipStream_t) {
+int launch_batched_forward(const BatchInst*, const uint2*, const int*, int*, int, int,
+                           hipStream_t) {
   return stub("batched");
 }
 int batched_grid_size(int) { return 1; }
