@@ -147,6 +147,39 @@ def test_batched_full_c4_instances(gjp, oracle_mod):
         assert_parity(got, want, 1e-5)
 
 
+def test_batched_fewer_groups_than_queues(gjp, oracle_mod):
+    """Instances of one view and one ray tile each (classes with fewer view
+    groups than the per-XCD queues, so most queues start empty and
+    workgroups take their items from other XCDs' queues), alone and mixed
+    with a larger instance: bitwise equal to the single launches (capture and
+    replay) and within the FP32 bound of the oracle."""
+    import torch
+    dev = cuda()
+    geoms = []
+    for k, (shape, n_u, n_v, beam) in enumerate((((7, 9, 11), 5, 6, "cone"),
+                                                  ((12, 8, 10), 3, 8, "parallel"),
+                                                  ((9, 9, 9), 4, 4, "cone"))):
+        gen = workloads.random_cone_views if beam == "cone" else workloads.random_parallel_views
+        geoms.append(gjp.Geometry(shape, gen(500 + k, 1, shape, n_u, n_v), n_u, n_v, beam=beam))
+    big = _small_instances(gjp, 230)[0]
+    gen = torch.Generator().manual_seed(330)
+    dtypes = [torch.float32, torch.bfloat16, torch.float32]
+    vols = [torch.rand(G.shape, generator=gen).to(dev).to(dt) for G, dt in zip(geoms, dtypes)]
+    vol_big = torch.rand(big.shape, generator=gen).to(dev)
+    for sel in ([0], [0, 1, 2], [0, 1, 2, 3]):
+        gs = [geoms[i] if i < 3 else big for i in sel]
+        vs = [vols[i] if i < 3 else vol_big for i in sel]
+        for rep in range(2):
+            note(f"batched tiny instances {sel} rep {rep}")
+            outs = gjp.forward_batched(vs, gs)
+            torch.cuda.synchronize()
+            for v, G, o in zip(vs, gs, outs):
+                assert torch.equal(o, gjp.forward(v, G))
+    for v, G in zip(vols, geoms):
+        want = oracle_mod.forward(_oracle_geom(oracle_mod, G), v.float().cpu().numpy())
+        assert_parity(gjp.forward(v, G).cpu().numpy(), want, 1e-5)
+
+
 def test_batched_tuned_tiles(gjp, oracle_mod):
     """Instances of the uneven workload with set tile shapes (three rays per
     lane, one ray, two rays per lane for 16-bit storage) in one batched
