@@ -456,6 +456,74 @@ def _analytic_sinogram_torch(cfg, G, dev):
     return out
 
 
+def _footprint_rays(og, voxel, margin=2):
+    """Every ray (view, iu, iv) that can carry weight on grid voxel `voxel`
+    of a cone-beam geometry: a sample weights the voxel only within one voxel
+    of it on both transverse axes, so its ray passes through the cube
+    [voxel - 1, voxel + 1]^3; the rays through that convex cube hit the
+    detector inside the box spanned by its eight corners' projections, taken
+    here widened by `margin` pixels."""
+    shape = np.asarray(og.shape, dtype=np.float64)
+    vs = np.asarray(og.voxel_size, dtype=np.float64)
+    ctr = np.asarray(og.center, dtype=np.float64)
+    corners = np.array([[voxel[0] + a, voxel[1] + b, voxel[2] + c]
+                        for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)], dtype=np.float64)
+    world = (corners - 0.5 * (shape - 1.0)) * vs + ctr
+    out = []
+    for vi, v in enumerate(og.views):
+        s, d00, du, dv = v[0:3], v[3:6], v[6:9], v[9:12]
+        uv = []
+        for p in world:
+            # s + t (p - s) = d00 + a du + b dv
+            M = np.stack([p - s, -du, -dv], axis=1)
+            t, a, b = np.linalg.solve(M, d00 - s)
+            uv.append((a, b))
+        uv = np.asarray(uv)
+        u0 = max(0, int(np.floor(uv[:, 0].min())) - margin)
+        u1 = min(og.n_u - 1, int(np.ceil(uv[:, 0].max())) + margin)
+        v0 = max(0, int(np.floor(uv[:, 1].min())) - margin)
+        v1 = min(og.n_v - 1, int(np.ceil(uv[:, 1].max())) + margin)
+        if u0 > u1 or v0 > v1:
+            continue
+        iu, iv = np.meshgrid(np.arange(u0, u1 + 1), np.arange(v0, v1 + 1), indexing="ij")
+        out.append(np.stack([np.full(iu.size, vi), iu.ravel(), iv.ravel()], axis=1))
+    return np.concatenate(out).astype(np.int32)
+
+
+@pytest.mark.slow
+def test_full_c3_adjoint_sampled_voxels(gjp, oracle_mod):
+    """The 512^3 / 720-view adjoint (value table and column gather, as the
+    benchmark runs it) on 12 sampled voxels against the oracle: (A^T y)[v] =
+    sum over rays of the ray's weight on v times y, the weights being the
+    oracle's forward projection of the one-hot volume e_v on every ray whose
+    detector footprint can reach v."""
+    import torch
+    dev = cuda()
+    cfg = workloads.config("c3")
+    G = gjp.Geometry.from_config(cfg)
+    og = oracle_mod.geometry_for(cfg)
+    gen = torch.Generator(device="cpu").manual_seed(60)
+    y = torch.rand(G.sino_shape, generator=gen)
+    note("c3 adjoint: GPU")
+    xb = gjp.back(y.to(dev), G).cpu().numpy()
+    y_np = y.numpy()
+    rng = np.random.default_rng(61)
+    voxels = [tuple(int(t) for t in rng.integers(0, 512, size=3)) for _ in range(10)]
+    voxels += [(0, 255, 511), (511, 0, 0)]   # grid corners and faces
+    onehot = np.zeros(cfg.shape, dtype=np.float32)
+    got, want = [], []
+    for v in voxels:
+        rays = _footprint_rays(og, v)
+        onehot[v] = 1.0
+        w = oracle_mod.forward_rays(og, onehot, rays)
+        onehot[v] = 0.0
+        want.append(float(np.dot(w, y_np[rays[:, 0], rays[:, 1], rays[:, 2]].astype(np.float64))))
+        got.append(float(xb[v]))
+        note(f"c3 adjoint: voxel {v}: {len(rays)} footprint rays, oracle {want[-1]:.6f}, "
+             f"GPU {got[-1]:.6f}")
+    assert_parity(np.array(got), np.array(want), 1e-5)
+
+
 @pytest.mark.slow
 def test_full_c3_differentiable(gjp, oracle_mod):
     """The differentiable-projector workload at full size: 512^3, 720 views,
