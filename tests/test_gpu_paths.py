@@ -491,25 +491,28 @@ def _footprint_rays(og, voxel, margin=2):
 
 
 @pytest.mark.slow
-def test_full_c3_adjoint_sampled_voxels(gjp, oracle_mod):
-    """The 512^3 / 720-view adjoint (value table and column gather, as the
-    benchmark runs it) on 12 sampled voxels against the oracle: (A^T y)[v] =
-    sum over rays of the ray's weight on v times y, the weights being the
-    oracle's forward projection of the one-hot volume e_v on every ray whose
-    detector footprint can reach v."""
+@pytest.mark.parametrize("name", ["c3", "t1"])
+def test_full_adjoint_sampled_voxels(gjp, oracle_mod, name):
+    """Full-size adjoints on 12 sampled voxels against the oracle: c3 (512^3,
+    720 views; value table and column gather, as the benchmark runs it) and
+    t1 (the paper's speed geometry, clipped to the cylinder; 16-byte ray
+    table). (A^T y)[v] = sum over rays of the ray's weight on v times y, the
+    weights being the oracle's forward projection of the one-hot volume e_v
+    on every ray whose detector footprint can reach v."""
     import torch
     dev = cuda()
-    cfg = workloads.config("c3")
+    cfg = workloads.config(name)
     G = gjp.Geometry.from_config(cfg)
     og = oracle_mod.geometry_for(cfg)
     gen = torch.Generator(device="cpu").manual_seed(60)
     y = torch.rand(G.sino_shape, generator=gen)
-    note("c3 adjoint: GPU")
+    note(f"{name} adjoint: GPU")
     xb = gjp.back(y.to(dev), G).cpu().numpy()
     y_np = y.numpy()
     rng = np.random.default_rng(61)
-    voxels = [tuple(int(t) for t in rng.integers(0, 512, size=3)) for _ in range(10)]
-    voxels += [(0, 255, 511), (511, 0, 0)]   # grid corners and faces
+    n = cfg.shape
+    voxels = [tuple(int(rng.integers(0, n[k])) for k in range(3)) for _ in range(10)]
+    voxels += [(0, n[1] // 2, n[2] - 1), (n[0] - 1, 0, 0)]   # grid faces and corners
     onehot = np.zeros(cfg.shape, dtype=np.float32)
     got, want = [], []
     for v in voxels:
@@ -519,7 +522,7 @@ def test_full_c3_adjoint_sampled_voxels(gjp, oracle_mod):
         onehot[v] = 0.0
         want.append(float(np.dot(w, y_np[rays[:, 0], rays[:, 1], rays[:, 2]].astype(np.float64))))
         got.append(float(xb[v]))
-        note(f"c3 adjoint: voxel {v}: {len(rays)} footprint rays, oracle {want[-1]:.6f}, "
+        note(f"{name} adjoint: voxel {v}: {len(rays)} footprint rays, oracle {want[-1]:.6f}, "
              f"GPU {got[-1]:.6f}")
     assert_parity(np.array(got), np.array(want), 1e-5)
 
